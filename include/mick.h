@@ -1,0 +1,204 @@
+/*
+ * mick.h - C ABI of libmick, the k-input RNS-CKKS ciphertext multiply on
+ * AMD MI355X (gfx950).
+ *
+ * The library multiplies k ciphertexts (k = 2..12) that share one secret key
+ * s and one modulus Q_l = q_0 ... q_{l-1}, relinearises the degree-k result
+ * with evaluation keys for s^2 .. s^k by hybrid key switching (ModUp by fast
+ * basis conversion, key inner product, ModDown), and applies k - 1
+ * rescalings combined into one multi-level rescale, following
+ * "Multi-Input Ciphertext Multiplication for Homomorphic Encryption"
+ * (Sec. II: RNS-CKKS, BConv, ModDown, rescale; Sec. III: the combined ModDown
+ * of eq. (product3); Sec. IV: the relocated ModDown of eqs. (moddown improved)
+ * and (scBconv) with P^-1 folded into the keys; Sec. V-A: eq. (d_u formula
+ * for n-ct mult), the keys of eq. (evks of ct mult for s^t) and eq. (extended
+ * relin); Sec. V-B: Algorithm 1 and eq. (multi rs)).
+ *
+ * Conventions (binding for every call):
+ *  - Residues are uint32, canonical in [0, m).  A polynomial over l limbs is
+ *    stored limb-major, uint32[l][N]; limb j holds the residues mod q_j.  A
+ *    ciphertext is uint32[2][l][N] (c0 then c1), in the NTT domain.
+ *  - Primes: q_i is the (i+1)-th largest prime below 2^30 with q = 1 mod 2N,
+ *    p_i the same below 2^31.  psi_m is the smallest x >= 2 with
+ *    x^N = -1 mod m.  NTT(a)[k] = a(psi^(2 brv(k) + 1)) mod m, brv the
+ *    log2(N)-bit reversal.
+ *  - Hybrid key switching with dnum digits: alpha = ceil(L / dnum); digit b
+ *    holds q_{b alpha} .. q_{min((b+1) alpha, l) - 1} at level l.
+ *  - Rescaling drops the highest active primes first (q_{l-1}, q_{l-2}, ...);
+ *    the dropped residue enters eq. (1-rs) as its representative in
+ *    [0, q_{l-1}), so mu rescales compute floor(x / (q_{l-1} ... q_{l-mu})).
+ *  - Random streams (keys, encryption noise; the paper fixes no generator):
+ *    SplitMix64 in counter mode, draw(key, n) = mix64(key + (n+1) G) with
+ *    G = 0x9E3779B97F4A7C15; a stream key is h = mix64(seed + G), then
+ *    h = mix64((h ^ w) + G) for w in (tag, a, b, c), the tag being up to 8
+ *    ASCII bytes little-endian.  Uniform mod m: draw(n) mod m (drawn directly
+ *    as NTT-domain values).  Ternary of weight h: partial Fisher-Yates, step
+ *    i swaps in position i + draw(2i) mod (N - i), sign + if draw(2i+1) is
+ *    even.  Gaussian (sigma = 3.2): the smallest x in [-19, 19] whose
+ *    cumulative threshold floor(2^64 C(x) / S) exceeds draw(n), the
+ *    cumulative sums of exp(-x^2 / 2 sigma^2) taken in FP64 from x = -19.
+ *    Secret weight h = 64.  Tags: SK; PK_A (limb); PK_E; EVK_A (t, b, row);
+ *    EVK_E (t, b); ENC_V, ENC_E0, ENC_E1 (ct_id).
+ *  - "Device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller.  Calls taking a
+ *    stream (a hipStream_t passed as void*, NULL = the default stream) are
+ *    asynchronous on that stream unless stated otherwise; the caller keeps
+ *    the buffers alive until the stream work completes.  The library keeps
+ *    no caller pointer after a call returns.
+ *  - Every call returns MICK_OK (0) or a negative status; nothing throws or
+ *    aborts.  mick_last_error() gives a thread-local message for the last
+ *    failing call on the calling thread.
+ */
+#ifndef MICK_H
+#define MICK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MICK_OK = 0,
+  MICK_E_ARG = -1,    /* NULL pointer, size or range error in an argument */
+  MICK_E_LEVEL = -2,  /* level < k, level > L, or mu >= level */
+  MICK_E_KEY = -3,    /* k larger than the key set's k_max */
+  MICK_E_NOMEM = -4,  /* device or host allocation failed */
+  MICK_E_HIP = -5,    /* a HIP runtime call failed (detail in mick_last_error) */
+  MICK_E_RANGE = -6,  /* a decrypted coefficient does not fit the output type */
+  MICK_E_WS = -7      /* workspace smaller than mick_workspace_bytes() */
+};
+
+typedef struct mick_params mick_params;
+typedef struct mick_keys mick_keys;
+
+const char* mick_strerror(int status);
+const char* mick_last_error(void);
+
+/* ---------------------------------------------------------------- params
+ * Ring degree N = 2^log_n (13 <= log_n <= 16), L ciphertext primes
+ * (1 <= L <= 60), K special primes (1 <= K <= 8), dnum digits with
+ * alpha = ceil(L / dnum) <= 8 primes each and at most 16 digits (the 64-bit
+ * sums of the basis conversions hold at most 8 products of 61 bits).
+ * Builds the primes, NTT twiddle tables, basis conversion tables and
+ * rescaling constants of Sec. II and Sec. V-B, and
+ * uploads them to the current HIP device (synchronous).  The handle is
+ * immutable and may be shared by threads and streams; free it with
+ * mick_params_destroy (NULL-safe) after all work using it has completed. */
+int mick_params_create(int log_n, int L, int K, int dnum, mick_params** out);
+void mick_params_destroy(mick_params* prm);
+/* Host copies of q_0..q_{L-1} (L values) and p_0..p_{K-1} (K values). */
+int mick_params_moduli(const mick_params* prm, uint32_t* q_host, uint32_t* p_host);
+/* log_n, L, K, dnum, alpha in out5_host[0..4]. */
+int mick_params_shape(const mick_params* prm, int* out5_host);
+
+/* ---------------------------------------------------------------- keys
+ * Seeded key generation (Sec. II public key; Sec. V-A eq. (evks of ct mult
+ * for s^t) generalised to dnum digits: the q_j rows of key (t, b) carry
+ * P G_b s^t with G_b = Qhat_b [Qhat_b^-1]_{Q_b}).  Keys for t = 2..k_max and
+ * every digit live in device memory owned by the handle; the device copy
+ * of each evaluation key has its q rows multiplied by [P^-1]_{q_j}
+ * (Sec. IV).  Synchronises `stream` before returning.  2 <= k_max <= 12. */
+int mick_keygen(const mick_params* prm, uint64_t seed, int k_max, void* stream, mick_keys** out);
+void mick_keys_destroy(mick_keys* keys);
+int mick_keys_kmax(const mick_keys* keys);
+/* Canonical key material copied to host memory (synchronous):
+ *  what = 0: secret s as int64 coefficients, N values (t, b ignored);
+ *  what = 1: public key (b, a), uint32[2][L][N], NTT domain;
+ *  what = 2: evaluation key (t, b) in the form of eq. (evks of ct mult for
+ *            s^t), unscaled, uint32[2][L+K][N], rows q_0..q_{L-1},
+ *            p_0..p_{K-1}, NTT domain. */
+int mick_keys_export(const mick_keys* keys, int what, int t, int b, void* host_out, void* stream);
+
+/* ---------------------------------------------------------------- codec
+ * CKKS canonical embedding in FP64 on the host (the paper does not describe
+ * encoding): N/2 slots, slot j at zeta_j = exp(i pi (5^j mod 2N) / N);
+ * m_i = round((2/N) Re sum_j scale z_j zeta_j^-i), half away from zero.
+ * n_slots must be N/2. */
+int mick_encode(const mick_params* prm, const double* re_host, const double* im_host, size_t n_slots,
+                double scale, int64_t* m_host);
+/* z_j = m(zeta_j) / scale, the inverse of mick_encode up to rounding. */
+int mick_decode(const mick_params* prm, const int64_t* m_host, double scale, double* re_host, double* im_host,
+                size_t n_slots);
+
+/* ---------------------------------------------------------------- encryption
+ * Public-key encryption (Sec. II): (c0, c1) = (m + v b + e0, v a + e1) at
+ * `level` (1..L), v ternary of weight N/2, e0 and e1 Gaussian, drawn from
+ * the streams of (seed, ct_id).  m_host: N int64 coefficients (already
+ * scaled).  ct_dev: device uint32[2][level][N], NTT domain.  Synchronises
+ * `stream` before returning (host inputs are staged). */
+int mick_encrypt(const mick_params* prm, const mick_keys* keys, const int64_t* m_host, int level, uint64_t seed,
+                 uint64_t ct_id, uint32_t* ct_dev, void* stream);
+/* Coefficient-domain residues of c0 + c1 s over q_0..q_{level-1}, copied to
+ * res_host uint32[level][N] (synchronous). */
+int mick_decrypt_residues(const mick_params* prm, const mick_keys* keys, const uint32_t* ct_dev, int level,
+                          uint32_t* res_host, void* stream);
+/* c0 + c1 s reconstructed by CRT over the active primes and centred into
+ * (-Q/2, Q/2]; MICK_E_RANGE if a coefficient needs more than 62 bits
+ * (Sec. II decryption, read over every active limb). */
+int mick_decrypt(const mick_params* prm, const mick_keys* keys, const uint32_t* ct_dev, int level, int64_t* m_host,
+                 void* stream);
+
+/* ---------------------------------------------------------------- hot path
+ * Operation codes for mick_workspace_bytes. */
+enum { MICK_OP_RELIN = 1, MICK_OP_RESCALE = 2, MICK_OP_MUL_RELIN_RESCALE = 3 };
+
+/* Device workspace needed by one call of `op` at (k, level); for
+ * MICK_OP_RESCALE, k is read as mu.  0 for invalid arguments. */
+size_t mick_workspace_bytes(const mick_params* prm, int op, int k, int level);
+
+/* Tensor product, eq. (d_u formula for n-ct mult): from k NTT-domain
+ * ciphertexts at `level` (cts_host: host array of k device pointers, each
+ * uint32[2][level][N]) computes d_0..d_k, d_t = sum over l in {0,1}^k with
+ * |l| = t of prod_u c^u_{l_u}, pointwise per limb.  d_dev: device
+ * uint32[k+1][level][N], NTT domain.  2 <= k <= 12. */
+int mick_mul_k(const mick_params* prm, const uint32_t* const* cts_host, int k, int level, uint32_t* d_dev,
+               void* stream);
+
+/* Relinearisation of eq. (extended relin) with one ModDown per output
+ * polynomial (Sec. III): (c0*, c1*) = (d_0, d_1) + ceil(P^-1 sum_t d_t ek_t)
+ * using the relocated ModDown of Sec. IV.  d_dev: device uint32[k+1][level]
+ * [N] (NTT domain, as written by mick_mul_k); ct_out_dev: device
+ * uint32[2][level][N], NTT domain.  ws: device workspace of at least
+ * mick_workspace_bytes(MICK_OP_RELIN, k, level) bytes. */
+int mick_relin_k(const mick_params* prm, const mick_keys* keys, const uint32_t* d_dev, int k, int level,
+                 uint32_t* ct_out_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* mu consecutive rescalings of an NTT-domain ciphertext by Algorithm 1
+ * (Sec. V-B): mu INTTs, the rescale chain of the dropped limbs, and
+ * level - mu NTTs.  ct_in_dev uint32[2][level][N] -> ct_out_dev
+ * uint32[2][level-mu][N] (must not overlap the input).  1 <= mu < level,
+ * mu <= 16. */
+int mick_rescale_multi(const mick_params* prm, const uint32_t* ct_in_dev, int level, int mu, uint32_t* ct_out_dev,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* The whole k-input multiply: tensor product, relinearisation with the
+ * relocated ModDown (Sec. IV), and mu = k - 1 rescalings combined in the
+ * coefficient domain by eq. (multi rs) followed by one NTT (the RS* of
+ * Sec. IV).  cts_host: host array of k device pointers uint32[2][level][N];
+ * ct_out_dev: device uint32[2][level-k+1][N], NTT domain.  k <= level <= L. */
+int mick_mul_relin_rescale(const mick_params* prm, const mick_keys* keys, const uint32_t* const* cts_host, int k,
+                           int level, uint32_t* ct_out_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* n_jobs (1..64) independent multiplies of the same (k, level) in one
+ * sequence of launches, each kernel covering every job; the key inner
+ * product reads each evaluation key element once for up to 8 jobs.
+ * cts_dev: device uint32[n_jobs][k][2][level][N] (job-major, contiguous);
+ * outs_dev: device uint32[n_jobs][2][level-k+1][N].  Results are
+ * bit-identical to n_jobs calls of mick_mul_relin_rescale.  ws: at least
+ * mick_batch_workspace_bytes() bytes. */
+size_t mick_batch_workspace_bytes(const mick_params* prm, int n_jobs, int k, int level);
+int mick_mul_relin_rescale_batch(const mick_params* prm, const mick_keys* keys, const uint32_t* cts_dev, int n_jobs,
+                                 int k, int level, uint32_t* outs_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* Forward / inverse negacyclic NTT of n_limbs limbs in place, limb i taken
+ * mod prime index first_prime + i (prime index j < L is q_j, L + i is p_i).
+ * Exposed for testing and benchmarking of the transform itself. */
+int mick_ntt(const mick_params* prm, uint32_t* data_dev, int n_limbs, int first_prime, int inverse, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MICK_H */

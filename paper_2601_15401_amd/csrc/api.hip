@@ -1,0 +1,773 @@
+// C ABI of libmick: parameter tables, key generation, encryption,
+// decryption and the orchestration of the k-input multiply.
+#include <string.h>
+
+#include <algorithm>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "host_math.h"
+#include "internal.h"
+#include "rns.h"
+
+using namespace mick;
+
+namespace mick {
+
+static thread_local std::string g_last_error;
+
+int set_error(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_error(hipError_t e, const char* what) {
+  if (e == hipSuccess) return MICK_OK;
+  return set_error(MICK_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace mick
+
+namespace {
+
+constexpr int kSecretWeight = 64;
+constexpr double kSigma = 3.2;
+
+#define MICK_TRY(expr)            \
+  do {                            \
+    int _st = (expr);             \
+    if (_st != MICK_OK) return _st; \
+  } while (0)
+
+#define MICK_HIP(expr, what) MICK_TRY(hip_error((expr), (what)))
+
+uint32_t inv_pow2_32(uint32_t m) {  // m^-1 mod 2^32 by Newton iteration
+  uint32_t x = m;
+  for (int i = 0; i < 5; i++) x *= 2 - m * x;
+  return x;
+}
+
+int brv(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; i++) r |= ((x >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+template <typename T>
+int upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  MICK_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+  MICK_HIP(hipStreamSynchronize(s), "upload sync");
+  return MICK_OK;
+}
+
+template <typename T>
+int dev_alloc(T** p, size_t count) {
+  hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return set_error(MICK_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return MICK_OK;
+}
+
+// Residues of an integer polynomial over the moduli with prime indices
+// [first, first + rows).
+std::vector<uint32_t> residues(const mick_params* prm, const int64_t* poly, int first, int rows) {
+  std::vector<uint32_t> out((size_t)rows * prm->N);
+  for (int r = 0; r < rows; r++) {
+    int64_t m = prm->mods[first + r];
+    for (int i = 0; i < prm->N; i++) {
+      int64_t v = poly[i] % m;
+      out[(size_t)r * prm->N + i] = (uint32_t)(v < 0 ? v + m : v);
+    }
+  }
+  return out;
+}
+
+int build_tables(mick_params* prm) {
+  const int N = prm->N, log_n = prm->log_n, L = prm->L, K = prm->K, E = L + K;
+  const int la = prm->split_a;
+  // ---- per-prime tables, one allocation
+  size_t n_mod = E, n_red = (size_t)E * 4, n_tw = (size_t)E * N * 2, n_fix = (size_t)E * 4,
+         n_rpow = (size_t)E * 2 * (kMaxK + 1);
+  size_t total = n_mod * 2 + n_red + n_tw * 2 + n_fix + n_rpow;
+  std::vector<uint32_t> h(total, 0);
+  uint32_t* h_mod = h.data();
+  uint32_t* h_minv = h_mod + n_mod;
+  uint32_t* h_red = h_minv + n_mod;
+  uint32_t* h_tw = h_red + n_red;
+  uint32_t* h_itw = h_tw + n_tw;
+  uint32_t* h_fix = h_itw + n_tw;
+  uint32_t* h_rpow = h_fix + n_fix;
+  prm->psi.resize(E);
+  std::vector<uint32_t> pw(2 * (size_t)N);
+  for (int r = 0; r < E; r++) {
+    const uint32_t m = prm->mods[r];
+    h_mod[r] = m;
+    h_minv[r] = inv_pow2_32(m);
+    const uint32_t r32 = (uint32_t)(((uint64_t)1 << 32) % m);
+    h_red[4 * r + 0] = m;
+    h_red[4 * r + 1] = r32;
+    h_red[4 * r + 2] = shoup_companion(r32, m);
+    h_red[4 * r + 3] = (uint32_t)(((uint64_t)1 << 32) / m);
+    const uint32_t psi = smallest_psi(m, N);
+    prm->psi[r] = psi;
+    uint64_t v = 1;
+    for (int i = 0; i < 2 * N; i++) {
+      pw[i] = (uint32_t)v;
+      v = v * psi % m;
+    }
+    uint32_t* tw = h_tw + (size_t)r * N * 2;
+    uint32_t* itw = h_itw + (size_t)r * N * 2;
+    for (int s = 0; s < log_n; s++) {
+      for (int b = 0; b < (1 << s); b++) {
+        int k = (1 << s) + b;
+        int e = brv(k, log_n);
+        uint32_t w = pw[e], wi = pw[(2 * N - e) % (2 * N)];
+        int pos = k;
+        if (s >= la) {  // pass-B stage: b = blk 2^sl + rr stored at rr 2^la + blk
+          int sl = s - la;
+          int blk = b >> sl, rr = b & ((1 << sl) - 1);
+          pos = (1 << s) + (rr << la) + blk;
+        }
+        tw[2 * pos] = w;
+        tw[2 * pos + 1] = shoup_companion(w, m);
+        itw[2 * pos] = wi;
+        itw[2 * pos + 1] = shoup_companion(wi, m);
+      }
+    }
+    const uint32_t ninv = (uint32_t)invmod(N, m);
+    const uint32_t w1 = pw[(2 * N - brv(1, log_n)) % (2 * N)];
+    const uint32_t w1n = (uint32_t)((uint64_t)w1 * ninv % m);
+    h_fix[4 * r + 0] = ninv;
+    h_fix[4 * r + 1] = shoup_companion(ninv, m);
+    h_fix[4 * r + 2] = w1n;
+    h_fix[4 * r + 3] = shoup_companion(w1n, m);
+    uint64_t R = ((uint64_t)1 << 32) % m, rp = 1;
+    for (int e = 0; e <= kMaxK; e++) {
+      h_rpow[(size_t)r * 2 * (kMaxK + 1) + 2 * e] = (uint32_t)rp;
+      h_rpow[(size_t)r * 2 * (kMaxK + 1) + 2 * e + 1] = shoup_companion((uint32_t)rp, m);
+      rp = rp * R % m;
+    }
+  }
+  MICK_TRY(dev_alloc((uint32_t**)&prm->d_tables, total));
+  uint32_t* d = (uint32_t*)prm->d_tables;
+  MICK_HIP(hipMemcpy(d, h.data(), total * 4, hipMemcpyHostToDevice), "table upload");
+  prm->dt.mod = d;
+  prm->dt.minv = d + n_mod;
+  prm->dt.red = reinterpret_cast<const Red64*>(d + 2 * n_mod);
+  prm->dt.tw = d + 2 * n_mod + n_red;
+  prm->dt.itw = prm->dt.tw + n_tw;
+  prm->dt.nfix = prm->dt.itw + n_tw;
+  prm->dt.rpow = prm->dt.nfix + n_fix;
+
+  // ---- ModUp tables per (level, digit)
+  const int a = prm->alpha;
+  std::vector<uint32_t> mu;
+  prm->modup_off.assign((size_t)L * prm->dnum, 0);
+  for (int level = 1; level <= L; level++) {
+    const int El = level + K;
+    for (int b = 0; b < prm->dnum; b++) {
+      int lo = b * a, hi = std::min(lo + a, level);
+      prm->modup_off[(size_t)(level - 1) * prm->dnum + b] = mu.size();
+      if (lo >= hi) continue;
+      int cnt = hi - lo;
+      std::vector<uint32_t> qh(cnt), qhs(cnt);
+      for (int j = 0; j < cnt; j++) {
+        uint32_t qj = prm->q[lo + j];
+        uint64_t x = 1;
+        for (int i = 0; i < cnt; i++)
+          if (i != j) x = x * invmod(prm->q[lo + i] % qj, qj) % qj;
+        qh[j] = (uint32_t)x;
+        qhs[j] = shoup_companion((uint32_t)x, qj);
+      }
+      mu.insert(mu.end(), qh.begin(), qh.end());
+      mu.insert(mu.end(), qhs.begin(), qhs.end());
+      for (int j = 0; j < cnt; j++) {
+        for (int e = 0; e < El; e++) {
+          uint32_t me = e < level ? prm->q[e] : prm->p[e - level];
+          uint64_t x = 1;
+          for (int i = 0; i < cnt; i++)
+            if (i != j) x = x * (prm->q[lo + i] % me) % me;
+          mu.push_back((uint32_t)x);
+        }
+      }
+    }
+  }
+  MICK_TRY(dev_alloc(&prm->d_modup, mu.size()));
+  MICK_HIP(hipMemcpy(prm->d_modup, mu.data(), mu.size() * 4, hipMemcpyHostToDevice), "modup upload");
+
+  // ---- ModDown tables and the chain constants q_d^-1 mod q_t
+  std::vector<uint32_t> md;
+  for (int i = 0; i < K; i++) {
+    uint32_t pi = prm->p[i];
+    uint64_t x = 1;
+    for (int i2 = 0; i2 < K; i2++)
+      if (i2 != i) x = x * invmod(prm->p[i2] % pi, pi) % pi;
+    md.push_back((uint32_t)x);
+    md.push_back(shoup_companion((uint32_t)x, pi));
+  }
+  for (int i = 0; i < K; i++)
+    for (int j = 0; j < L; j++) md.push_back((uint32_t)invmod(prm->p[i] % prm->q[j], prm->q[j]));
+  for (int d2 = 0; d2 < L; d2++) {
+    for (int t = 0; t < L; t++) {
+      uint32_t v = d2 == t ? 0 : (uint32_t)invmod(prm->q[d2] % prm->q[t], prm->q[t]);
+      md.push_back(v);
+      md.push_back(shoup_companion(v, prm->q[t]));
+    }
+  }
+  MICK_TRY(dev_alloc(&prm->d_moddown, md.size()));
+  MICK_HIP(hipMemcpy(prm->d_moddown, md.data(), md.size() * 4, hipMemcpyHostToDevice), "moddown upload");
+
+  // ---- rescale constants g^{mu,t}_eta per (level, mu), eq. (g(u,t,eta))
+  std::vector<uint32_t> rs;
+  prm->rescale_off.assign((size_t)(L + 1) * (L + 1), 0);
+  for (int level = 2; level <= L; level++) {
+    for (int m2 = 1; m2 < level && m2 <= 16; m2++) {
+      prm->rescale_off[(size_t)level * (L + 1) + m2] = rs.size();
+      int top = level - m2;
+      std::vector<uint32_t> g((size_t)top * m2);
+      for (int eta = 0; eta < top; eta++) {
+        uint32_t qe = prm->q[eta];
+        uint64_t x = 1;
+        for (int t = level - m2; t < level; t++) {
+          x = x * invmod(prm->q[t] % qe, qe) % qe;
+          g[(size_t)eta * m2 + (t - (level - m2))] = (uint32_t)x;
+        }
+        rs.push_back((uint32_t)x);  // g^{mu,l-1}_eta
+        rs.push_back(shoup_companion((uint32_t)x, qe));
+      }
+      rs.insert(rs.end(), g.begin(), g.end());
+    }
+  }
+  MICK_TRY(dev_alloc(&prm->d_rescale, rs.size()));
+  if (!rs.empty()) MICK_HIP(hipMemcpy(prm->d_rescale, rs.data(), rs.size() * 4, hipMemcpyHostToDevice), "rs upload");
+
+  // host constants
+  prm->pinv_q.resize(L);
+  prm->p_mod_q.resize(L);
+  for (int j = 0; j < L; j++) {
+    uint64_t P = 1;
+    for (int i = 0; i < K; i++) P = P * (prm->p[i] % prm->q[j]) % prm->q[j];
+    prm->p_mod_q[j] = (uint32_t)P;
+    prm->pinv_q[j] = (uint32_t)invmod(P, prm->q[j]);
+  }
+  return MICK_OK;
+}
+
+MdArgs md_args(const mick_params* prm, int level, int mu) {
+  MdArgs A{};
+  A.md = prm->d_moddown;
+  A.qinvq = prm->d_moddown + 2 * prm->K + (size_t)prm->K * prm->L;
+  A.rs = mu > 0 ? prm->d_rescale + prm->rescale_off[(size_t)level * (prm->L + 1) + mu] : nullptr;
+  A.log_n = prm->log_n;
+  A.level = level;
+  A.L = prm->L;
+  A.K = prm->K;
+  A.E = level + prm->K;
+  return A;
+}
+
+struct Layout {  // per-job workspace of the multiply, in elements
+  size_t D, dcoef, X, acc, total;
+};
+
+Layout mul_layout(const mick_params* prm, int k, int level) {
+  const size_t N = prm->N;
+  const int E = level + prm->K, B = digits_at(prm, level);
+  Layout l;
+  l.D = 0;
+  l.dcoef = l.D + (size_t)(k + 1) * level * N;
+  l.X = l.dcoef + (size_t)(k - 1) * level * N;
+  l.acc = l.X + (size_t)(k - 1) * B * E * N;
+  l.total = l.acc + 2 * (size_t)E * N;
+  return l;
+}
+
+int check_mul(const mick_params* prm, const mick_keys* keys, int k, int level) {
+  if (!prm || !keys) return set_error(MICK_E_ARG, "NULL params or keys");
+  if (keys->prm != prm) return set_error(MICK_E_ARG, "keys belong to other params");
+  if (k < 2 || k > kMaxK) return set_error(MICK_E_ARG, "k must be in 2..12");
+  if (level < k || level > prm->L) return set_error(MICK_E_LEVEL, "level must be in k..L");
+  if (k > keys->k_max) return set_error(MICK_E_KEY, "k exceeds the key set's k_max");
+  return MICK_OK;
+}
+
+// Relinearisation and rescale of jobs whose tensor products are already in
+// the workspace (D at the start of each job block).
+int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int level, int mu, uint32_t* ws,
+                     size_t job_stride, int n_jobs, uint32_t* out, size_t out_job, hipStream_t s) {
+  const Layout lay = mul_layout(prm, k, level);
+  const int N = prm->N, L = prm->L, K = prm->K, E = level + K, B = digits_at(prm, level);
+  // ModUp: INTT of d_2..d_k
+  LimbMap m = simple_map(prm, 0, level);
+  m.job_stride = (long long)job_stride;
+  MICK_TRY(ntt_launch(prm, ws + lay.D + 2 * (size_t)level * N, ws + lay.dcoef, m, (k - 1) * level, n_jobs, true, s));
+  // basis conversion from each digit
+  ModupArgs ma{};
+  ma.tab = prm->d_modup;
+  for (int b = 0; b < B; b++) ma.tab_off[b] = (int)prm->modup_off[(size_t)(level - 1) * prm->dnum + b];
+  ma.log_n = prm->log_n;
+  ma.level = level;
+  ma.L = L;
+  ma.E = E;
+  ma.B = B;
+  ma.alpha = prm->alpha;
+  ma.dcoef_job = (long long)job_stride;
+  ma.x_job = (long long)job_stride;
+  MICK_TRY(launch_modup(prm, ws + lay.dcoef, ws + lay.X, ma, k, n_jobs, s));
+  // NTT of the converted limbs (the digit's own limbs are skipped)
+  LimbMap mx{};
+  mx.period = E;
+  mx.group_stride = (long long)E * N;
+  mx.split = level;
+  mx.off_lo = 0;
+  mx.off_hi = L - level;
+  mx.skip_groups = B;
+  mx.skip_alpha = prm->alpha;
+  mx.skip_level = level;
+  mx.job_stride = (long long)job_stride;
+  MICK_TRY(ntt_launch(prm, ws + lay.X, ws + lay.X, mx, (k - 1) * B * E, n_jobs, false, s));
+  // key inner product, combined over t, with D_l added on the q rows
+  KipArgs ka{};
+  ka.log_n = prm->log_n;
+  ka.level = level;
+  ka.L = L;
+  ka.E = E;
+  ka.B = B;
+  ka.alpha = prm->alpha;
+  ka.dnum = prm->dnum;
+  ka.k = k;
+  ka.n_jobs = n_jobs;
+  ka.key_poly = (long long)(L + K) * N;
+  ka.d_job = ka.x_job = ka.acc_job = (long long)job_stride;
+  MICK_TRY(launch_kip(prm, ws + lay.D, ws + lay.X, keys->d_evk, ws + lay.acc, ka, s));
+  // relocated ModDown: INTT of every accumulator limb
+  LimbMap ma2{};
+  ma2.period = E;
+  ma2.group_stride = (long long)E * N;
+  ma2.split = level;
+  ma2.off_lo = 0;
+  ma2.off_hi = L - level;
+  ma2.job_stride = (long long)job_stride;
+  MICK_TRY(ntt_launch(prm, ws + lay.acc, ws + lay.acc, ma2, 2 * E, n_jobs, true, s));
+  // scaled BConv, subtraction and the combined rescale, then the final NTT
+  MdArgs A = md_args(prm, level, mu);
+  A.acc_job = (long long)job_stride;
+  A.out_job = (long long)out_job;
+  MICK_TRY(launch_moddown_rs(prm, ws + lay.acc, out, A, mu, n_jobs, s));
+  LimbMap mo = simple_map(prm, 0, level - mu);
+  mo.job_stride = (long long)out_job;
+  MICK_TRY(ntt_launch(prm, out, out, mo, 2 * (level - mu), n_jobs, false, s));
+  return MICK_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char* mick_strerror(int status) {
+  switch (status) {
+    case MICK_OK: return "ok";
+    case MICK_E_ARG: return "invalid argument";
+    case MICK_E_LEVEL: return "invalid level";
+    case MICK_E_KEY: return "k exceeds the key set";
+    case MICK_E_NOMEM: return "out of memory";
+    case MICK_E_HIP: return "HIP runtime error";
+    case MICK_E_RANGE: return "value out of range";
+    case MICK_E_WS: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+const char* mick_last_error(void) { return g_last_error.c_str(); }
+
+int mick_params_create(int log_n, int L, int K, int dnum, mick_params** out) {
+  if (!out) return set_error(MICK_E_ARG, "NULL out");
+  *out = nullptr;
+  if (log_n < 13 || log_n > 16) return set_error(MICK_E_ARG, "log_n must be in 13..16");
+  if (L < 1 || L > 60 || K < 1 || K > kMaxKp || dnum < 1 || dnum > L)
+    return set_error(MICK_E_ARG, "need 1 <= L <= 60, 1 <= K <= 8, 1 <= dnum <= L");
+  const int alpha = (L + dnum - 1) / dnum;
+  if (alpha > kMaxAlpha || (L + alpha - 1) / alpha > 16)
+    return set_error(MICK_E_ARG, "ceil(L / dnum) must be at most 8");
+  std::unique_ptr<mick_params> p(new mick_params());
+  p->log_n = log_n;
+  p->N = 1 << log_n;
+  p->L = L;
+  p->K = K;
+  p->dnum = dnum;
+  p->alpha = alpha;
+  p->q = ntt_primes(30, 2 * (uint64_t)p->N, L);
+  p->p = ntt_primes(31, 2 * (uint64_t)p->N, K);
+  if ((int)p->q.size() < L || (int)p->p.size() < K) return set_error(MICK_E_ARG, "not enough NTT-friendly primes");
+  p->mods = p->q;
+  p->mods.insert(p->mods.end(), p->p.begin(), p->p.end());
+  static const int split_a[17] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 7, 7, 8, 8};
+  p->split_a = split_a[log_n];
+  p->split_b = log_n - p->split_a;
+  MICK_HIP(hipGetDevice(&p->device), "hipGetDevice");
+  int st = build_tables(p.get());
+  if (st != MICK_OK) {
+    mick_params_destroy(p.release());
+    return st;
+  }
+  *out = p.release();
+  return MICK_OK;
+}
+
+void mick_params_destroy(mick_params* prm) {
+  if (!prm) return;
+  if (prm->d_tables) (void)hipFree(prm->d_tables);
+  if (prm->d_modup) (void)hipFree(prm->d_modup);
+  if (prm->d_moddown) (void)hipFree(prm->d_moddown);
+  if (prm->d_rescale) (void)hipFree(prm->d_rescale);
+  delete prm;
+}
+
+int mick_params_moduli(const mick_params* prm, uint32_t* q_host, uint32_t* p_host) {
+  if (!prm || !q_host || !p_host) return set_error(MICK_E_ARG, "NULL argument");
+  memcpy(q_host, prm->q.data(), prm->L * 4);
+  memcpy(p_host, prm->p.data(), prm->K * 4);
+  return MICK_OK;
+}
+
+int mick_params_shape(const mick_params* prm, int* out5) {
+  if (!prm || !out5) return set_error(MICK_E_ARG, "NULL argument");
+  out5[0] = prm->log_n;
+  out5[1] = prm->L;
+  out5[2] = prm->K;
+  out5[3] = prm->dnum;
+  out5[4] = prm->alpha;
+  return MICK_OK;
+}
+
+int mick_keygen(const mick_params* prm, uint64_t seed, int k_max, void* stream, mick_keys** out) {
+  if (!prm || !out) return set_error(MICK_E_ARG, "NULL argument");
+  *out = nullptr;
+  if (k_max < 2 || k_max > kMaxK) return set_error(MICK_E_ARG, "k_max must be in 2..12");
+  hipStream_t s = (hipStream_t)stream;
+  const int N = prm->N, L = prm->L, K = prm->K, E = L + K;
+  const size_t NE = (size_t)E * N;
+  std::unique_ptr<mick_keys> keys(new mick_keys());
+  keys->prm = prm;
+  keys->k_max = k_max;
+  keys->seed = seed;
+  keys->s = sample_ternary(stream_key(seed, "SK"), N, kSecretWeight);
+  MICK_TRY(dev_alloc(&keys->d_S, NE));
+  MICK_TRY(dev_alloc(&keys->d_pk, 2 * (size_t)L * N));
+  MICK_TRY(dev_alloc(&keys->d_evk, (size_t)(k_max - 1) * prm->dnum * 2 * NE));
+  uint32_t *tE = nullptr, *tA = nullptr, *tSt = nullptr, *tRow = nullptr;
+  auto cleanup = [&]() {
+    if (tE) (void)hipFree(tE);
+    if (tA) (void)hipFree(tA);
+    if (tSt) (void)hipFree(tSt);
+    if (tRow) (void)hipFree(tRow);
+  };
+  int st = [&]() -> int {
+    MICK_TRY(dev_alloc(&tE, NE));
+    MICK_TRY(dev_alloc(&tA, NE));
+    MICK_TRY(dev_alloc(&tSt, NE));
+    MICK_TRY(dev_alloc(&tRow, (size_t)E * 4));
+    const GaussTable gt = gauss_table(kSigma);
+    // S = NTT(s) over every modulus
+    MICK_TRY(upload(keys->d_S, residues(prm, keys->s.data(), 0, E), s));
+    MICK_TRY(ntt_launch(prm, keys->d_S, keys->d_S, simple_map(prm, 0, E), E, 1, false, s));
+    // public key
+    std::vector<uint32_t> ha((size_t)L * N);
+    for (int j = 0; j < L; j++) sample_uniform(stream_key(seed, "PK_A", j), prm->q[j], N, ha.data() + (size_t)j * N);
+    MICK_TRY(upload(keys->d_pk + (size_t)L * N, ha, s));
+    std::vector<int64_t> e = sample_gauss(stream_key(seed, "PK_E"), N, gt);
+    MICK_TRY(upload(tE, residues(prm, e.data(), 0, L), s));
+    MICK_TRY(ntt_launch(prm, tE, tE, simple_map(prm, 0, L), L, 1, false, s));
+    MICK_TRY(launch_pk(prm, tE, keys->d_pk + (size_t)L * N, keys->d_S, keys->d_pk, s));
+    // evaluation keys for s^t, t = 2..k_max, one per digit
+    MICK_HIP(hipMemcpyAsync(tSt, keys->d_S, NE * 4, hipMemcpyDeviceToDevice, s), "copy S");
+    std::vector<uint32_t> hrow((size_t)E * 4);
+    std::vector<uint32_t> hA(NE);
+    for (int t = 2; t <= k_max; t++) {
+      MICK_TRY(launch_mul_rows(prm, tSt, keys->d_S, E, s));
+      for (int b = 0; b < prm->dnum; b++) {
+        for (int r = 0; r < E; r++)
+          sample_uniform(stream_key(seed, "EVK_A", t, b, r), prm->mods[r], N, hA.data() + (size_t)r * N);
+        MICK_TRY(upload(tA, hA, s));
+        std::vector<int64_t> ee = sample_gauss(stream_key(seed, "EVK_E", t, b), N, gt);
+        MICK_TRY(upload(tE, residues(prm, ee.data(), 0, E), s));
+        MICK_TRY(ntt_launch(prm, tE, tE, simple_map(prm, 0, E), E, 1, false, s));
+        const int lo = b * prm->alpha, hi = std::min(lo + prm->alpha, L);
+        for (int r = 0; r < E; r++) {
+          uint32_t m = prm->mods[r];
+          uint32_t g = (r < L && r >= lo && r < hi) ? prm->p_mod_q[r] : 0;
+          uint32_t f = r < L ? prm->pinv_q[r] : 1;
+          hrow[4 * r + 0] = g;
+          hrow[4 * r + 1] = f;
+          hrow[4 * r + 2] = shoup_companion(f, m);
+          hrow[4 * r + 3] = 0;
+        }
+        MICK_TRY(upload(tRow, hrow, s));
+        uint32_t* k0 = keys->d_evk + evk_offset(prm, t, b, 0);
+        uint32_t* k1 = keys->d_evk + evk_offset(prm, t, b, 1);
+        MICK_TRY(launch_evk(prm, tE, tA, keys->d_S, tSt, k0, k1, tRow, s));
+      }
+    }
+    MICK_HIP(hipStreamSynchronize(s), "keygen sync");
+    return MICK_OK;
+  }();
+  cleanup();
+  if (st != MICK_OK) {
+    mick_keys_destroy(keys.release());
+    return st;
+  }
+  *out = keys.release();
+  return MICK_OK;
+}
+
+void mick_keys_destroy(mick_keys* keys) {
+  if (!keys) return;
+  if (keys->d_S) (void)hipFree(keys->d_S);
+  if (keys->d_pk) (void)hipFree(keys->d_pk);
+  if (keys->d_evk) (void)hipFree(keys->d_evk);
+  delete keys;
+}
+
+int mick_keys_kmax(const mick_keys* keys) { return keys ? keys->k_max : MICK_E_ARG; }
+
+int mick_keys_export(const mick_keys* keys, int what, int t, int b, void* host_out, void* stream) {
+  if (!keys || !host_out) return set_error(MICK_E_ARG, "NULL argument");
+  const mick_params* prm = keys->prm;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t N = prm->N;
+  const int L = prm->L, E = prm->L + prm->K;
+  if (what == 0) {
+    memcpy(host_out, keys->s.data(), N * 8);
+    return MICK_OK;
+  }
+  if (what == 1) {
+    MICK_HIP(hipMemcpyAsync(host_out, keys->d_pk, 2 * L * N * 4, hipMemcpyDeviceToHost, s), "export pk");
+    MICK_HIP(hipStreamSynchronize(s), "export sync");
+    return MICK_OK;
+  }
+  if (what == 2) {
+    if (t < 2 || t > keys->k_max || b < 0 || b >= prm->dnum) return set_error(MICK_E_ARG, "no such key");
+    uint32_t* o = (uint32_t*)host_out;
+    MICK_HIP(hipMemcpyAsync(o, keys->d_evk + evk_offset(prm, t, b, 0), 2 * E * N * 4, hipMemcpyDeviceToHost, s),
+             "export evk");
+    MICK_HIP(hipStreamSynchronize(s), "export sync");
+    for (int l = 0; l < 2; l++)
+      for (int r = 0; r < L; r++) {  // undo the [P^-1] of the q rows
+        uint64_t P = prm->p_mod_q[r], m = prm->q[r];
+        uint32_t* row = o + ((size_t)l * E + r) * N;
+        for (size_t i = 0; i < N; i++) row[i] = (uint32_t)(row[i] * P % m);
+      }
+    return MICK_OK;
+  }
+  return set_error(MICK_E_ARG, "unknown export kind");
+}
+
+int mick_encode(const mick_params* prm, const double* re, const double* im, size_t n_slots, double scale,
+                int64_t* m_host) {
+  if (!prm || !re || !im || !m_host) return set_error(MICK_E_ARG, "NULL argument");
+  if (n_slots != (size_t)prm->N / 2) return set_error(MICK_E_ARG, "n_slots must be N/2");
+  ckks_encode(prm->N, re, im, scale, m_host);
+  return MICK_OK;
+}
+
+int mick_decode(const mick_params* prm, const int64_t* m_host, double scale, double* re, double* im,
+                size_t n_slots) {
+  if (!prm || !re || !im || !m_host) return set_error(MICK_E_ARG, "NULL argument");
+  if (n_slots != (size_t)prm->N / 2) return set_error(MICK_E_ARG, "n_slots must be N/2");
+  ckks_decode(prm->N, m_host, scale, re, im);
+  return MICK_OK;
+}
+
+int mick_encrypt(const mick_params* prm, const mick_keys* keys, const int64_t* m_host, int level, uint64_t seed,
+                 uint64_t ct_id, uint32_t* ct_dev, void* stream) {
+  if (!prm || !keys || !m_host || !ct_dev) return set_error(MICK_E_ARG, "NULL argument");
+  if (level < 1 || level > prm->L) return set_error(MICK_E_LEVEL, "level must be in 1..L");
+  hipStream_t s = (hipStream_t)stream;
+  const int N = prm->N;
+  const size_t LN = (size_t)level * N;
+  const GaussTable gt = gauss_table(kSigma);
+  std::vector<int64_t> v = sample_ternary(stream_key(seed, "ENC_V", ct_id), N, N / 2);
+  std::vector<int64_t> e0 = sample_gauss(stream_key(seed, "ENC_E0", ct_id), N, gt);
+  std::vector<int64_t> e1 = sample_gauss(stream_key(seed, "ENC_E1", ct_id), N, gt);
+  std::vector<uint32_t> hm = residues(prm, m_host, 0, level), he0 = residues(prm, e0.data(), 0, level);
+  for (size_t i = 0; i < LN; i++) {
+    uint32_t m = prm->q[i / N];
+    hm[i] = (uint32_t)(((uint64_t)hm[i] + he0[i]) % m);
+  }
+  uint32_t* tmp = nullptr;
+  MICK_TRY(dev_alloc(&tmp, 3 * LN));
+  int st = [&]() -> int {
+    MICK_TRY(upload(tmp, residues(prm, v.data(), 0, level), s));
+    MICK_TRY(upload(tmp + LN, hm, s));
+    MICK_TRY(upload(tmp + 2 * LN, residues(prm, e1.data(), 0, level), s));
+    LimbMap mp = simple_map(prm, 0, level);
+    MICK_TRY(ntt_launch(prm, tmp, tmp, mp, 3 * level, 1, false, s));
+    MICK_TRY(launch_enc(prm, tmp, tmp + LN, tmp + 2 * LN, keys->d_pk, ct_dev, level, s));
+    MICK_HIP(hipStreamSynchronize(s), "encrypt sync");
+    return MICK_OK;
+  }();
+  (void)hipFree(tmp);
+  return st;
+}
+
+static int decrypt_res(const mick_params* prm, const mick_keys* keys, const uint32_t* ct_dev, int level,
+                       uint32_t* res_host, hipStream_t s) {
+  const size_t LN = (size_t)level * prm->N;
+  uint32_t* tmp = nullptr;
+  MICK_TRY(dev_alloc(&tmp, LN));
+  int st = [&]() -> int {
+    MICK_TRY(launch_dec(prm, ct_dev, keys->d_S, tmp, level, s));
+    MICK_TRY(ntt_launch(prm, tmp, tmp, simple_map(prm, 0, level), level, 1, true, s));
+    MICK_HIP(hipMemcpyAsync(res_host, tmp, LN * 4, hipMemcpyDeviceToHost, s), "decrypt copy");
+    MICK_HIP(hipStreamSynchronize(s), "decrypt sync");
+    return MICK_OK;
+  }();
+  (void)hipFree(tmp);
+  return st;
+}
+
+int mick_decrypt_residues(const mick_params* prm, const mick_keys* keys, const uint32_t* ct_dev, int level,
+                          uint32_t* res_host, void* stream) {
+  if (!prm || !keys || !ct_dev || !res_host) return set_error(MICK_E_ARG, "NULL argument");
+  if (level < 1 || level > prm->L) return set_error(MICK_E_LEVEL, "level must be in 1..L");
+  return decrypt_res(prm, keys, ct_dev, level, res_host, (hipStream_t)stream);
+}
+
+int mick_decrypt(const mick_params* prm, const mick_keys* keys, const uint32_t* ct_dev, int level, int64_t* m_host,
+                 void* stream) {
+  if (!prm || !keys || !ct_dev || !m_host) return set_error(MICK_E_ARG, "NULL argument");
+  if (level < 1 || level > prm->L) return set_error(MICK_E_LEVEL, "level must be in 1..L");
+  const int N = prm->N;
+  std::vector<uint32_t> res((size_t)level * N);
+  MICK_TRY(decrypt_res(prm, keys, ct_dev, level, res.data(), (hipStream_t)stream));
+  std::vector<uint32_t> qs(prm->q.begin(), prm->q.begin() + level);
+  Crt crt(qs);
+  std::vector<uint32_t> col(level);
+  for (int i = 0; i < N; i++) {
+    for (int j = 0; j < level; j++) col[j] = res[(size_t)j * N + i];
+    if (!crt.centred(col.data(), &m_host[i])) return set_error(MICK_E_RANGE, "coefficient exceeds 62 bits");
+  }
+  return MICK_OK;
+}
+
+size_t mick_workspace_bytes(const mick_params* prm, int op, int k, int level) {
+  if (!prm || level < 1 || level > prm->L) return 0;
+  const size_t N = prm->N;
+  switch (op) {
+    case MICK_OP_MUL_RELIN_RESCALE:
+      if (k < 2 || k > kMaxK || level < k) return 0;
+      return mul_layout(prm, k, level).total * 4;
+    case MICK_OP_RELIN:
+      if (k < 2 || k > kMaxK || level < k) return 0;
+      return mul_layout(prm, k, level).total * 4;
+    case MICK_OP_RESCALE:
+      if (k < 1 || k >= level) return 0;
+      return 2 * (size_t)level * N * 4;
+    default: return 0;
+  }
+}
+
+int mick_mul_k(const mick_params* prm, const uint32_t* const* cts_host, int k, int level, uint32_t* d_dev,
+               void* stream) {
+  if (!prm || !cts_host || !d_dev) return set_error(MICK_E_ARG, "NULL argument");
+  if (k < 2 || k > kMaxK) return set_error(MICK_E_ARG, "k must be in 2..12");
+  if (level < 1 || level > prm->L) return set_error(MICK_E_LEVEL, "level must be in 1..L");
+  CtPtrs in{};
+  for (int u = 0; u < k; u++) {
+    if (!cts_host[u]) return set_error(MICK_E_ARG, "NULL ciphertext pointer");
+    in.p[u] = cts_host[u];
+  }
+  return launch_tensor(prm, in, 0, k, level, d_dev, 0, 1, (hipStream_t)stream);
+}
+
+int mick_relin_k(const mick_params* prm, const mick_keys* keys, const uint32_t* d_dev, int k, int level,
+                 uint32_t* ct_out_dev, void* ws, size_t ws_bytes, void* stream) {
+  MICK_TRY(check_mul(prm, keys, k, level));
+  if (!d_dev || !ct_out_dev || !ws) return set_error(MICK_E_ARG, "NULL argument");
+  if (ws_bytes < mick_workspace_bytes(prm, MICK_OP_MUL_RELIN_RESCALE, k, level))
+    return set_error(MICK_E_WS, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const Layout lay = mul_layout(prm, k, level);
+  uint32_t* w = (uint32_t*)ws;
+  // stage D in the workspace so that one layout serves every step
+  MICK_HIP(hipMemcpyAsync(w + lay.D, d_dev, (size_t)(k + 1) * level * prm->N * 4, hipMemcpyDeviceToDevice, s),
+           "stage d");
+  return relin_rescale_ws(prm, keys, k, level, 0, w, lay.total, 1, ct_out_dev, 0, s);
+}
+
+int mick_rescale_multi(const mick_params* prm, const uint32_t* ct_in_dev, int level, int mu, uint32_t* ct_out_dev,
+                       void* ws, size_t ws_bytes, void* stream) {
+  if (!prm || !ct_in_dev || !ct_out_dev || !ws) return set_error(MICK_E_ARG, "NULL argument");
+  if (level < 2 || level > prm->L || mu < 1 || mu >= level) return set_error(MICK_E_LEVEL, "need 1 <= mu < level <= L");
+  if (mu > 16) return set_error(MICK_E_ARG, "mu must be at most 16");
+  if (ws_bytes < mick_workspace_bytes(prm, MICK_OP_RESCALE, mu, level)) return set_error(MICK_E_WS, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t N = prm->N;
+  const int top = level - mu;
+  uint32_t* topc = (uint32_t*)ws;
+  uint32_t* bb = topc + 2 * (size_t)mu * N;
+  // Algorithm 1 step 1: INTT of the mu dropped limbs
+  MICK_HIP(hipMemcpy2DAsync(topc, (size_t)mu * N * 4, ct_in_dev + (size_t)top * N, (size_t)level * N * 4,
+                            (size_t)mu * N * 4, 2, hipMemcpyDeviceToDevice, s),
+           "stage dropped limbs");
+  LimbMap mt = simple_map(prm, top, mu);
+  MICK_TRY(ntt_launch(prm, topc, topc, mt, 2 * mu, 1, true, s));
+  // steps 2 and 3: chain, sums, NTT, combine
+  MdArgs A = md_args(prm, level, mu);
+  MICK_TRY(launch_rs_sums(prm, topc, bb, A, mu, s));
+  MICK_TRY(ntt_launch(prm, bb, bb, simple_map(prm, 0, top), 2 * top, 1, false, s));
+  return launch_rs_combine(prm, ct_in_dev, bb, ct_out_dev, A, mu, s);
+}
+
+int mick_mul_relin_rescale(const mick_params* prm, const mick_keys* keys, const uint32_t* const* cts_host, int k,
+                           int level, uint32_t* ct_out_dev, void* ws, size_t ws_bytes, void* stream) {
+  MICK_TRY(check_mul(prm, keys, k, level));
+  if (!cts_host || !ct_out_dev || !ws) return set_error(MICK_E_ARG, "NULL argument");
+  if (ws_bytes < mick_workspace_bytes(prm, MICK_OP_MUL_RELIN_RESCALE, k, level))
+    return set_error(MICK_E_WS, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const Layout lay = mul_layout(prm, k, level);
+  uint32_t* w = (uint32_t*)ws;
+  CtPtrs in{};
+  for (int u = 0; u < k; u++) {
+    if (!cts_host[u]) return set_error(MICK_E_ARG, "NULL ciphertext pointer");
+    in.p[u] = cts_host[u];
+  }
+  MICK_TRY(launch_tensor(prm, in, 0, k, level, w + lay.D, 0, 1, s));
+  return relin_rescale_ws(prm, keys, k, level, k - 1, w, lay.total, 1, ct_out_dev, 0, s);
+}
+
+size_t mick_batch_workspace_bytes(const mick_params* prm, int n_jobs, int k, int level) {
+  if (n_jobs < 1 || n_jobs > kMaxJobs) return 0;
+  return (size_t)n_jobs * mick_workspace_bytes(prm, MICK_OP_MUL_RELIN_RESCALE, k, level);
+}
+
+int mick_mul_relin_rescale_batch(const mick_params* prm, const mick_keys* keys, const uint32_t* cts_dev, int n_jobs,
+                                 int k, int level, uint32_t* outs_dev, void* ws, size_t ws_bytes, void* stream) {
+  MICK_TRY(check_mul(prm, keys, k, level));
+  if (!cts_dev || !outs_dev || !ws) return set_error(MICK_E_ARG, "NULL argument");
+  if (n_jobs < 1 || n_jobs > kMaxJobs) return set_error(MICK_E_ARG, "n_jobs must be in 1..64");
+  if (ws_bytes < mick_batch_workspace_bytes(prm, n_jobs, k, level)) return set_error(MICK_E_WS, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t N = prm->N;
+  const Layout lay = mul_layout(prm, k, level);
+  uint32_t* w = (uint32_t*)ws;
+  CtPtrs in{};
+  const size_t ct_elems = 2 * (size_t)level * N;
+  for (int u = 0; u < k; u++) in.p[u] = cts_dev + (size_t)u * ct_elems;
+  MICK_TRY(launch_tensor(prm, in, (long long)(k * ct_elems), k, level, w + lay.D, (long long)lay.total, n_jobs, s));
+  const size_t out_job = 2 * (size_t)(level - k + 1) * N;
+  return relin_rescale_ws(prm, keys, k, level, k - 1, w, lay.total, n_jobs, outs_dev, out_job, s);
+}
+
+int mick_ntt(const mick_params* prm, uint32_t* data_dev, int n_limbs, int first_prime, int inverse, void* stream) {
+  if (!prm || !data_dev) return set_error(MICK_E_ARG, "NULL argument");
+  if (n_limbs < 1 || first_prime < 0 || first_prime + n_limbs > prm->L + prm->K)
+    return set_error(MICK_E_ARG, "limb range outside the prime set");
+  return ntt_launch(prm, data_dev, data_dev, simple_map(prm, first_prime, n_limbs), n_limbs, 1, inverse != 0,
+                    (hipStream_t)stream);
+}
+
+}  // extern "C"

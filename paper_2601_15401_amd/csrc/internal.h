@@ -1,0 +1,96 @@
+// Internal structures shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mick.h"
+#include "modarith.h"
+
+namespace mick {
+
+constexpr int kMaxK = 12;     // largest k of a k-input multiply
+constexpr int kMaxJobs = 64;  // jobs per batched launch sequence
+
+// Device pointers to the per-prime tables.  Prime index j < L is q_j,
+// L + i is p_i.
+struct DevTables {
+  const uint32_t* mod;    // [L+K]
+  const uint32_t* minv;   // [L+K] m^-1 mod 2^32 (Montgomery)
+  const Red64* red;       // [L+K]
+  const uint32_t* tw;     // [L+K][N][2] forward twiddle, Shoup companion; pass-B stages transposed
+  const uint32_t* itw;    // [L+K][N][2] inverse twiddles, same layout
+  const uint32_t* nfix;   // [L+K][4]: N^-1, Shoup; (stage-0 inverse twiddle) N^-1, Shoup
+  const uint32_t* rpow;   // [L+K][2*(kMaxK+1)]: R^e mod m and Shoup, e = 0..kMaxK
+};
+
+// Where the limbs of one transform launch live and which prime each uses.
+// Limb i: group g = i / period, position pos = i % period; data at
+// base + g * group_stride + pos * N; prime pos + off_lo if pos < split, else
+// pos + off_hi.  With skip_groups > 0 the group cycles over that many digits
+// and positions inside the digit's own primes are skipped (ModUp outputs).
+struct LimbMap {
+  int period;
+  long long group_stride;
+  int split, off_lo, off_hi;
+  int skip_groups, skip_alpha, skip_level;
+  long long job_stride;  // elements between jobs (blockIdx.z)
+};
+
+struct mick_params_impl;
+
+}  // namespace mick
+
+struct mick_params {
+  int log_n, N, L, K, dnum, alpha;
+  std::vector<uint32_t> q, p, mods;  // mods = q ++ p
+  int device;
+  // device allocations
+  void* d_tables = nullptr;  // one allocation for all per-prime tables
+  mick::DevTables dt;
+  // ModUp basis conversion tables per (level, digit): offsets into d_modup
+  uint32_t* d_modup = nullptr;
+  std::vector<size_t> modup_off;  // index (level - 1) * dnum + digit
+  // ModDown tables: phinv (+Shoup) [K][2], pinvq [K][L]
+  uint32_t* d_moddown = nullptr;
+  // rescale tables per (level, mu)
+  uint32_t* d_rescale = nullptr;
+  std::vector<size_t> rescale_off;  // index level * (L + 1) + mu
+  // P^-1 and P mod q_j (host)
+  std::vector<uint32_t> pinv_q, p_mod_q;
+  // host copies of psi per prime
+  std::vector<uint32_t> psi;
+  int split_a, split_b;  // log2 rows of the two NTT passes
+};
+
+struct mick_keys {
+  const mick_params* prm;
+  int k_max;
+  uint64_t seed;
+  std::vector<int64_t> s;  // host copy of the secret
+  uint32_t* d_S = nullptr;    // [L+K][N] NTT(s)
+  uint32_t* d_pk = nullptr;   // [2][L][N] (b, a)
+  uint32_t* d_evk = nullptr;  // [t = 2..k_max][dnum][2][L+K][N], q rows x P^-1
+};
+
+namespace mick {
+
+// Error reporting (thread-local message).
+int set_error(int status, const std::string& msg);
+int hip_error(hipError_t e, const char* what);
+
+// Transforms (ntt.hip).  src may equal dst.
+int ntt_launch(const mick_params* prm, const uint32_t* src, uint32_t* dst, const LimbMap& map, int n_limbs, int n_jobs,
+               bool inverse, hipStream_t s);
+LimbMap simple_map(const mick_params* prm, int first_prime, int n_limbs);
+
+inline size_t evk_offset(const mick_params* prm, int t, int b, int l) {
+  size_t limbs = (size_t)(prm->L + prm->K);
+  return ((((size_t)(t - 2) * prm->dnum + b) * 2 + l) * limbs) << prm->log_n;
+}
+
+inline int digits_at(const mick_params* prm, int level) { return (level + prm->alpha - 1) / prm->alpha; }
+
+}  // namespace mick

@@ -1,0 +1,60 @@
+// Device modular arithmetic for moduli m < 2^31 (32-bit residues).
+//
+// Three forms are used:
+//  * Shoup multiplication by a constant w < m with companion
+//    w' = floor(w 2^32 / m): y w - floor(y w' / 2^32) m is congruent to y w and
+//    lies in [0, 2m) for any 32-bit y.  Used for twiddles and table constants.
+//  * Montgomery multiplication of two variables with R = 2^32: for T = a b
+//    < m 2^32, REDC(T) = T R^-1 mod m in [0, m).  Used where both operands
+//    vary (tensor product); the accumulated R^-1 factors are removed once.
+//  * 64-bit multiply-accumulate followed by one reduction of the 64-bit sum
+//    (basis conversion, key inner product, rescale sums).
+// All values stay below 2^32 because 2m < 2^32.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mick {
+
+// [0, 2m) -> [0, m): x - m wraps above x exactly when x < m.
+__device__ __forceinline__ uint32_t red1(uint32_t x, uint32_t m) { return min(x, x - m); }
+
+__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t m) { return red1(a + b, m); }
+
+__device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t m) { return red1(a - b + m, m); }
+
+// Result in [0, 2m), congruent to y * w.
+__device__ __forceinline__ uint32_t shoup_lazy(uint32_t y, uint32_t w, uint32_t wsh, uint32_t m) {
+  return y * w - __umulhi(y, wsh) * m;
+}
+
+__device__ __forceinline__ uint32_t shoup(uint32_t y, uint32_t w, uint32_t wsh, uint32_t m) {
+  return red1(shoup_lazy(y, w, wsh, m), m);
+}
+
+// a * b * 2^-32 mod m in [0, m), for a * b < m * 2^32.  minv = m^-1 mod 2^32.
+__device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t m, uint32_t minv) {
+  uint64_t t = (uint64_t)a * b;
+  uint32_t lo = (uint32_t)t, hi = (uint32_t)(t >> 32);
+  uint32_t mh = __umulhi(lo * minv, m);
+  uint32_t r = hi - mh;
+  return hi < mh ? r + m : r;
+}
+
+// Per-modulus constants for reducing a full 64-bit value.
+struct Red64 {
+  uint32_t m;
+  uint32_t r32;    // 2^32 mod m
+  uint32_t r32sh;  // floor(r32 2^32 / m)
+  uint32_t onesh;  // floor(2^32 / m)
+};
+
+// x mod m for any 64-bit x: x = hi 2^32 + lo, both halves reduced by Shoup.
+__device__ __forceinline__ uint32_t reduce64(uint64_t x, const Red64& c) {
+  uint32_t hi = (uint32_t)(x >> 32), lo = (uint32_t)x;
+  uint32_t a = shoup(hi, c.r32, c.r32sh, c.m);
+  uint32_t b = red1(lo - __umulhi(lo, c.onesh) * c.m, c.m);
+  return red1(a + b, c.m);
+}
+
+}  // namespace mick

@@ -1,0 +1,56 @@
+// Launch arguments and launchers of the pointwise RNS kernels.
+#pragma once
+#include "internal.h"
+
+namespace mick {
+
+constexpr int kMaxAlpha = 8;  // primes per key-switching digit
+constexpr int kMaxKp = 8;     // special primes p_i
+
+struct CtPtrs {
+  const uint32_t* p[kMaxK];
+};
+
+struct ModupArgs {
+  const uint32_t* tab;  // modup table block of this level
+  int tab_off[16];      // per digit offset inside `tab`
+  int log_n, level, L, E, B, alpha;
+  long long dcoef_job, x_job;
+};
+
+struct KipArgs {
+  int log_n, level, L, E, B, alpha, dnum, k, n_jobs;
+  long long key_poly;  // elements per key polynomial ((L+K) N)
+  long long d_job, x_job, acc_job;
+};
+
+struct MdArgs {
+  const uint32_t* md;     // [K][2] phat_i^-1 (+Shoup), then [K][L] p_i^-1 mod q_j
+  const uint32_t* qinvq;  // [L][L][2] q_d^-1 mod q_t (+Shoup)
+  const uint32_t* rs;     // (level, mu) block: [top][2] g^{mu,l-1}_eta (+Shoup), [top][mu] g^{mu,t}_eta
+  int log_n, level, L, K, E;
+  long long acc_job, out_job;
+};
+
+int launch_tensor(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level, uint32_t* D,
+                  long long d_job_stride, int n_jobs, hipStream_t s);
+int launch_modup(const mick_params* prm, const uint32_t* dcoef, uint32_t* X, const ModupArgs& A, int k, int n_jobs,
+                 hipStream_t s);
+int launch_kip(const mick_params* prm, const uint32_t* D, const uint32_t* X, const uint32_t* evk, uint32_t* acc,
+               const KipArgs& A, hipStream_t s);
+int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out, const MdArgs& A, int mu, int n_jobs,
+                      hipStream_t s);
+int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout, const MdArgs& A, int mu,
+                   hipStream_t s);
+int launch_rs_combine(const mick_params* prm, const uint32_t* Ain, const uint32_t* Bn, uint32_t* out, const MdArgs& A,
+                      int mu, hipStream_t s);
+int launch_pk(const mick_params* prm, const uint32_t* E, const uint32_t* a, const uint32_t* S, uint32_t* b,
+              hipStream_t s);
+int launch_mul_rows(const mick_params* prm, uint32_t* X, const uint32_t* Y, int rows, hipStream_t s);
+int launch_evk(const mick_params* prm, const uint32_t* E, const uint32_t* a, const uint32_t* S, const uint32_t* St,
+               uint32_t* k0, uint32_t* k1, const uint32_t* rowc, hipStream_t s);
+int launch_enc(const mick_params* prm, const uint32_t* V, const uint32_t* M0, const uint32_t* E1, const uint32_t* pk,
+               uint32_t* ct, int level, hipStream_t s);
+int launch_dec(const mick_params* prm, const uint32_t* ct, const uint32_t* S, uint32_t* X, int level, hipStream_t s);
+
+}  // namespace mick

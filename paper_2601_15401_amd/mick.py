@@ -1,0 +1,285 @@
+"""Python binding of libmick (ctypes).  Argument marshalling only: every step
+of the multiply runs in the library's HIP kernels.  PyTorch provides device
+memory (uint32 data held in int32 tensors) and the current HIP stream.
+
+The library must be built (``python -m paper_2601_15401_amd.build``); when it
+is missing every call raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+import torch  # loads the HIP runtime that libmick then shares
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmick.so")
+
+OP_RELIN, OP_RESCALE, OP_MUL_RELIN_RESCALE = 1, 2, 3
+
+_c_u32p = ctypes.POINTER(ctypes.c_uint32)
+_c_i64p = ctypes.POINTER(ctypes.c_int64)
+_c_dblp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+# name: (restype, argtypes)
+_SIGS = {
+    "mick_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "mick_last_error": (ctypes.c_char_p, []),
+    "mick_params_create": (ctypes.c_int, [ctypes.c_int] * 4 + [ctypes.POINTER(_vp)]),
+    "mick_params_destroy": (None, [_vp]),
+    "mick_params_moduli": (ctypes.c_int, [_vp, _c_u32p, _c_u32p]),
+    "mick_params_shape": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    "mick_keygen": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "mick_keys_destroy": (None, [_vp]),
+    "mick_keys_kmax": (ctypes.c_int, [_vp]),
+    "mick_keys_export": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "mick_encode": (ctypes.c_int, [_vp, _c_dblp, _c_dblp, ctypes.c_size_t, ctypes.c_double, _c_i64p]),
+    "mick_decode": (ctypes.c_int, [_vp, _c_i64p, ctypes.c_double, _c_dblp, _c_dblp, ctypes.c_size_t]),
+    "mick_encrypt": (ctypes.c_int, [_vp, _vp, _c_i64p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp]),
+    "mick_decrypt_residues": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _c_u32p, _vp]),
+    "mick_decrypt": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _c_i64p, _vp]),
+    "mick_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "mick_mul_k": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "mick_relin_k": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp]),
+    "mick_rescale_multi": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp]),
+    "mick_mul_relin_rescale": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp,
+                                              ctypes.c_size_t, _vp]),
+    "mick_batch_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "mick_mul_relin_rescale_batch": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                                    _vp, ctypes.c_size_t, _vp]),
+    "mick_ntt": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+}
+
+_lib = None
+
+
+class MickError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        lib = load()
+        msg = "%s: %s (%s)" % (where, lib.mick_strerror(status).decode(), lib.mick_last_error().decode())
+        super().__init__(msg)
+
+
+def load():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmick.so is not built (run python -m paper_2601_15401_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise MickError(status, where)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.int32:
+        raise ValueError("expected a contiguous int32 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_empty(*shape):
+    return torch.empty(*shape, dtype=torch.int32, device="cuda")
+
+
+def to_numpy_u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def from_numpy_u32(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+class Params:
+    def __init__(self, log_n: int, L: int, K: int, dnum: int):
+        lib = load()
+        h = _vp()
+        _check(lib.mick_params_create(log_n, L, K, dnum, ctypes.byref(h)), "mick_params_create")
+        self._h = h
+        self.log_n, self.L, self.K, self.dnum = log_n, L, K, dnum
+        self.N = 1 << log_n
+        q = (ctypes.c_uint32 * L)()
+        p = (ctypes.c_uint32 * K)()
+        _check(lib.mick_params_moduli(h, q, p), "mick_params_moduli")
+        self.q, self.p = list(q), list(p)
+        shape = (ctypes.c_int * 5)()
+        _check(lib.mick_params_shape(h, shape), "mick_params_shape")
+        self.alpha = shape[4]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mick_params_destroy(self._h)
+            self._h = None
+
+    def workspace_bytes(self, op: int, k: int, level: int) -> int:
+        return load().mick_workspace_bytes(self._h, op, k, level)
+
+
+class Keys:
+    def __init__(self, prm: Params, seed: int, k_max: int):
+        h = _vp()
+        _check(load().mick_keygen(prm.handle, seed, k_max, _stream(), ctypes.byref(h)), "mick_keygen")
+        self._h, self.prm, self.k_max, self.seed = h, prm, k_max, seed
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            torch.cuda.synchronize()
+            _lib.mick_keys_destroy(self._h)
+            self._h = None
+
+    def export_secret(self) -> np.ndarray:
+        out = np.empty(self.prm.N, dtype=np.int64)
+        _check(load().mick_keys_export(self._h, 0, 0, 0, out.ctypes.data_as(_vp), _stream()), "export")
+        return out
+
+    def export_pk(self) -> np.ndarray:
+        out = np.empty((2, self.prm.L, self.prm.N), dtype=np.uint32)
+        _check(load().mick_keys_export(self._h, 1, 0, 0, out.ctypes.data_as(_vp), _stream()), "export")
+        return out
+
+    def export_evk(self, t: int, b: int) -> np.ndarray:
+        out = np.empty((2, self.prm.L + self.prm.K, self.prm.N), dtype=np.uint32)
+        _check(load().mick_keys_export(self._h, 2, t, b, out.ctypes.data_as(_vp), _stream()), "export")
+        return out
+
+
+def encode(prm: Params, re: np.ndarray, im: np.ndarray, scale: float) -> np.ndarray:
+    re = np.ascontiguousarray(re, dtype=np.float64)
+    im = np.ascontiguousarray(im, dtype=np.float64)
+    out = np.empty(prm.N, dtype=np.int64)
+    _check(load().mick_encode(prm.handle, re.ctypes.data_as(_c_dblp), im.ctypes.data_as(_c_dblp), re.size, scale,
+                              out.ctypes.data_as(_c_i64p)), "mick_encode")
+    return out
+
+
+def decode(prm: Params, m: np.ndarray, scale: float):
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    re = np.empty(prm.N // 2)
+    im = np.empty(prm.N // 2)
+    _check(load().mick_decode(prm.handle, m.ctypes.data_as(_c_i64p), scale, re.ctypes.data_as(_c_dblp),
+                              im.ctypes.data_as(_c_dblp), re.size), "mick_decode")
+    return re, im
+
+
+def encrypt(prm: Params, keys: Keys, m: np.ndarray, level: int, seed: int, ct_id: int, out=None) -> torch.Tensor:
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    if out is None:
+        out = _dev_empty(2, level, prm.N)
+    _check(load().mick_encrypt(prm.handle, keys.handle, m.ctypes.data_as(_c_i64p), level, seed, ct_id, _ptr(out),
+                               _stream()), "mick_encrypt")
+    return out
+
+
+def decrypt_residues(prm: Params, keys: Keys, ct: torch.Tensor, level: int) -> np.ndarray:
+    out = np.empty((level, prm.N), dtype=np.uint32)
+    _check(load().mick_decrypt_residues(prm.handle, keys.handle, _ptr(ct), level, out.ctypes.data_as(_c_u32p),
+                                        _stream()), "mick_decrypt_residues")
+    return out
+
+
+def decrypt(prm: Params, keys: Keys, ct: torch.Tensor, level: int) -> np.ndarray:
+    out = np.empty(prm.N, dtype=np.int64)
+    _check(load().mick_decrypt(prm.handle, keys.handle, _ptr(ct), level, out.ctypes.data_as(_c_i64p), _stream()),
+           "mick_decrypt")
+    return out
+
+
+def workspace(prm: Params, op: int, k: int, level: int) -> torch.Tensor:
+    nbytes = prm.workspace_bytes(op, k, level)
+    if nbytes == 0:
+        raise ValueError("invalid (op, k, level)")
+    return _dev_empty(nbytes // 4)
+
+
+def mul_k(prm: Params, cts: Sequence[torch.Tensor], level: int, out=None) -> torch.Tensor:
+    k = len(cts)
+    if out is None:
+        out = _dev_empty(k + 1, level, prm.N)
+    arr = (_vp * k)(*[_ptr(c).value for c in cts])
+    _check(load().mick_mul_k(prm.handle, arr, k, level, _ptr(out), _stream()), "mick_mul_k")
+    return out
+
+
+def relin_k(prm: Params, keys: Keys, d: torch.Tensor, k: int, level: int, out=None, ws=None) -> torch.Tensor:
+    if out is None:
+        out = _dev_empty(2, level, prm.N)
+    if ws is None:
+        ws = workspace(prm, OP_RELIN, k, level)
+    _check(load().mick_relin_k(prm.handle, keys.handle, _ptr(d), k, level, _ptr(out), _ptr(ws), ws.numel() * 4,
+                               _stream()), "mick_relin_k")
+    return out
+
+
+def rescale_multi(prm: Params, ct: torch.Tensor, level: int, mu: int, out=None, ws=None) -> torch.Tensor:
+    if out is None:
+        out = _dev_empty(2, level - mu, prm.N)
+    if ws is None:
+        ws = workspace(prm, OP_RESCALE, mu, level)
+    _check(load().mick_rescale_multi(prm.handle, _ptr(ct), level, mu, _ptr(out), _ptr(ws), ws.numel() * 4,
+                                     _stream()), "mick_rescale_multi")
+    return out
+
+
+def mul_relin_rescale(prm: Params, keys: Keys, cts: Sequence[torch.Tensor], level: int, out=None,
+                      ws=None) -> torch.Tensor:
+    k = len(cts)
+    if out is None:
+        out = _dev_empty(2, level - k + 1, prm.N)
+    if ws is None:
+        ws = workspace(prm, OP_MUL_RELIN_RESCALE, k, level)
+    arr = (_vp * k)(*[_ptr(c).value for c in cts])
+    _check(load().mick_mul_relin_rescale(prm.handle, keys.handle, arr, k, level, _ptr(out), _ptr(ws),
+                                         ws.numel() * 4, _stream()), "mick_mul_relin_rescale")
+    return out
+
+
+def batch_workspace(prm: Params, n_jobs: int, k: int, level: int) -> torch.Tensor:
+    nbytes = load().mick_batch_workspace_bytes(prm.handle, n_jobs, k, level)
+    if nbytes == 0:
+        raise ValueError("invalid (n_jobs, k, level)")
+    return _dev_empty(nbytes // 4)
+
+
+def mul_relin_rescale_batch(prm: Params, keys: Keys, cts: torch.Tensor, level: int, out=None,
+                            ws=None) -> torch.Tensor:
+    """cts: [n_jobs, k, 2, level, N] int32 device tensor."""
+    n_jobs, k = cts.shape[0], cts.shape[1]
+    if tuple(cts.shape[2:]) != (2, level, prm.N):
+        raise ValueError("cts must be [n_jobs, k, 2, level, N]")
+    if out is None:
+        out = _dev_empty(n_jobs, 2, level - k + 1, prm.N)
+    if ws is None:
+        ws = batch_workspace(prm, n_jobs, k, level)
+    _check(load().mick_mul_relin_rescale_batch(prm.handle, keys.handle, _ptr(cts), n_jobs, k, level, _ptr(out),
+                                               _ptr(ws), ws.numel() * 4, _stream()), "mick_mul_relin_rescale_batch")
+    return out
+
+
+def ntt(prm: Params, data: torch.Tensor, first_prime: int, inverse: bool = False) -> torch.Tensor:
+    """In-place transform of data [n_limbs, N]; limb i uses prime index first_prime + i."""
+    _check(load().mick_ntt(prm.handle, _ptr(data), data.shape[0], first_prime, int(inverse), _stream()), "mick_ntt")
+    return data
