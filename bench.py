@@ -1,0 +1,269 @@
+"""Throughput of the k-input RNS-CKKS multiply on one MI355X.
+
+Workload (default): the eight-input multiply at N = 2^16 with 32 ciphertext
+primes of 30 bits, 8 special primes of 31 bits, dnum = 4, scale 2^30, keys
+for s^2..s^8, as a batch of 8 independent multiplies (tensor product,
+relinearisation, combined 7-level rescale) per step.  Inputs are encryptions
+of seeded synthetic messages (slots uniform in [-1, 1)^2), resident in HBM
+before timing starts.
+
+One JSON line on stdout: the metric (batched ct-mults/s), the plain
+per-multiply launch rate beside it, per-step latency percentiles, the
+roofline of the dominant kernel from HIP events recorded on its stream
+during the timed steps, and the CPU oracle timed on one multiply.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one 32-bit integer VALU op per lane
+# per clock (gfx950 issues v_mul_lo/hi_u32 at full rate, measured).
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+WORKLOADS = {
+    # name: (log_n, L, K, dnum, k, level, batch)
+    "n16_k8_b8": (16, 32, 8, 4, 8, 32, 8),
+    "n15_k4_b16": (15, 16, 4, 4, 4, 16, 16),
+    "n13_k3": (13, 3, 1, 3, 3, 3, 1),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def site_work(site, N, k, level, K, alpha, jobs):
+    """Algorithmic bytes and 32-bit integer ops of one launch at `site`.
+
+    Bytes: every input element read once and every output element written once
+    (4 bytes each); key material counted once per launch.  Ops: a radix-2
+    butterfly mod q is counted as 9 VALU operations (Shoup product 4, lazy
+    reduction 2, add 1, subtract-and-offset 2)."""
+    E = level + K
+    B = -(-level // alpha)
+    mu = k - 1
+    limb = 4.0 * N
+    new_limbs = (k - 1) * (B * E - level)  # ModUp outputs that are transformed
+    bfly = 9.0
+    if site.startswith("ntt_modup"):
+        n = jobs * new_limbs
+        return 2 * limb * n, n * (N / 2) * 8 * bfly
+    if site.startswith("intt_d"):
+        n = jobs * (k - 1) * level
+        return 2 * limb * n, n * (N / 2) * 8 * bfly
+    if site.startswith("intt_acc"):
+        n = jobs * 2 * E
+        return 2 * limb * n, n * (N / 2) * 8 * bfly
+    if site.startswith("ntt_out"):
+        n = jobs * 2 * (level - mu)
+        return 2 * limb * n, n * (N / 2) * 8 * bfly
+    if site == "tensor":
+        n_in, n_out = jobs * k * 2 * level, jobs * (k + 1) * level
+        return limb * (n_in + n_out), jobs * level * N * (k * (k + 1) - 2) * 7.0
+    if site == "modup_bconv":
+        n_in, n_out = jobs * (k - 1) * level, jobs * new_limbs
+        return limb * (n_in + n_out), jobs * new_limbs * N * (2 * alpha + 10.0)
+    if site == "kip":
+        x = jobs * (k - 1) * B * E
+        keys = math.ceil(jobs / 8) * (k - 1) * B * 2 * E
+        return limb * (x + keys + jobs * 2 * level + jobs * 2 * E), jobs * (k - 1) * B * E * N * 2 * 2.0
+    if site == "moddown_rescale":
+        return limb * jobs * (2 * E + 2 * (level - mu)), jobs * 2 * (level - mu) * N * (2 * (K + mu) + 30.0)
+    return 0.0, 0.0
+
+
+def roofline(prof, steps, N, k, level, K, alpha, jobs):
+    """Dominant kernel by total time; passes A and B of a transform share one
+    kernel symbol and are reported together."""
+    merged = {}
+    for site, (ms, cnt) in prof.items():
+        key = site.split(".")[0]
+        t, c = merged.get(key, (0.0, 0))
+        merged[key] = (t + ms, c + cnt)
+    table = []
+    for site, (ms, cnt) in merged.items():
+        b, ops = site_work(site, N, k, level, K, alpha, jobs)
+        per = 2 if site.startswith(("ntt", "intt")) else 1   # launches per call
+        avg_s = ms / cnt / 1e3
+        table.append((ms, site, cnt, avg_s, b / avg_s / 1e9 if b else 0.0, ops / per / avg_s / 1e12 if ops else 0.0,
+                      b, ops / per))
+    table.sort(reverse=True)
+    for ms, site, cnt, avg_s, gbs, tops, b, ops in table:
+        log("  %-16s %8.3f ms/step %4d launches  avg %8.1f us  %7.0f GB/s (%4.1f%% HBM)  %6.2f Tops (%4.1f%% ALU)"
+            % (site, ms / steps, cnt, avg_s * 1e6, gbs, 100 * gbs / HBM_PEAK_GBS, tops, 100 * tops / ALU_PEAK_TOPS))
+    ms, site, cnt, avg_s, gbs, tops, b, ops = table[0]
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tops / ALU_PEAK_TOPS
+    if site.startswith(("ntt", "intt")) or alu_frac > hbm_frac:
+        return {"kernel": site, "bound": "alu", "achieved": round(tops, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(alu_frac, 4), "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": b,
+                "hbm_frac_at_algorithmic_bytes": round(hbm_frac, 4)}
+    return {"kernel": site, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm_frac, 4), "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
+            "algorithmic_bytes_per_launch": b}
+
+
+def mult_bytes(N, k, level, K, alpha, jobs):
+    """Algorithmic HBM bytes of one multiply in a batch of `jobs` sharing keys:
+    k inputs read, the evaluation keys read once per batch, output written."""
+    B = -(-level // alpha)
+    E = level + K
+    inputs = k * 2 * level * N * 4
+    keys = (k - 1) * B * 2 * E * N * 4 / jobs
+    out = 2 * (level - k + 1) * N * 4
+    return inputs + keys + out
+
+
+def cpu_baseline(log_n, L, K, dnum, k, level):
+    """The oracle (exact numpy/Python-int path) on one multiply, one core."""
+    from oracle import keys as okeys, mult, params as oparams
+    prm = oparams.make_params(log_n, L, K, dnum)
+    log("cpu baseline: oracle keygen ...")
+    ks = okeys.keygen(prm, 99, k)
+    rng = np.random.default_rng(99)
+    cts = [np.stack([np.stack([rng.integers(0, q, prm.N, dtype=np.int64).astype(np.uint64) for q in prm.q[:level]])
+                     for _ in range(2)]) for _ in range(k)]
+    log("cpu baseline: timing one multiply ...")
+    t0 = time.perf_counter()
+    mult.mul_relin_rescale(prm, ks, cts, level)
+    dt = time.perf_counter() - t0
+    log("cpu baseline: %.1f s per multiply" % dt)
+    return {"value": round(1.0 / dt, 5), "unit": "ct-mults/s", "cores": 1, "kind": "oracle",
+            "sample": "one %d-input multiply at N=2^%d, level %d (tensor, relin, %d-level rescale), %.1f s; "
+                      "host %s" % (k, log_n, level, k - 1, dt, platform.processor() or platform.machine())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="n16_k8_b8", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="copy a MIB-sized buffer once before timing (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2601_15401_amd import mick
+
+    log_n, L, K, dnum, k, level, jobs = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    log("params N=2^%d L=%d K=%d dnum=%d; keygen k_max=%d ..." % (log_n, L, K, dnum, k))
+    prm = mick.Params(log_n, L, K, dnum)
+    keys = mick.Keys(prm, 3, k)
+    N = prm.N
+    scale = 2.0 ** 30
+    rng = np.random.default_rng(2024)
+    cts = torch.empty(jobs, k, 2, level, N, dtype=torch.int32, device="cuda")
+    log("encrypting %d inputs ..." % (jobs * k))
+    for j in range(jobs):
+        for u in range(k):
+            re = rng.uniform(-1, 1, N // 2)
+            im = rng.uniform(-1, 1, N // 2)
+            m = mick.encode(prm, re, im, scale)
+            mick.encrypt(prm, keys, m, level, 3, j * k + u, out=cts[j, u])
+    out = torch.empty(jobs, 2, level - k + 1, N, dtype=torch.int32, device="cuda")
+    ws = mick.batch_workspace(prm, jobs, k, level)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration:
+        a = torch.ones(args.copy_calibration << 18, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy of %d MiB done" % args.copy_calibration)
+        del a, b
+    log("warmup %d steps ..." % args.warmup)
+    mick.profile_enable(True)
+    for _ in range(args.warmup):
+        mick.mul_relin_rescale_batch(prm, keys, cts, level, out=out, ws=ws)
+    torch.cuda.synchronize()
+    mick.profile_collect()
+
+    log("timing %d batched steps ..." % args.steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        mick.mul_relin_rescale_batch(prm, keys, cts, level, out=out, ws=ws)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = mick.profile_collect()
+    mick.profile_enable(False)
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    gpu_s = float(step_ms.sum()) / 1e3
+    value = jobs * args.steps / gpu_s
+    log("batched: %.3f ms/step, %.1f ct-mults/s (host wall %.3f s)" % (step_ms.mean(), value, wall))
+    rl = roofline(prof, args.steps, N, k, level, K, prm.alpha, jobs)
+
+    plain = None
+    if not args.no_plain:
+        ws1 = mick.workspace(prm, mick.OP_MUL_RELIN_RESCALE, k, level)
+        lists = [[cts[j, u] for u in range(k)] for j in range(jobs)]
+        for j in range(jobs):
+            mick.mul_relin_rescale(prm, keys, lists[j], level, out=out[j], ws=ws1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            for j in range(jobs):
+                mick.mul_relin_rescale(prm, keys, lists[j], level, out=out[j], ws=ws1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / (args.steps * jobs)
+        plain = {"value": round(1e3 / pms, 2), "unit": "ct-mults/s", "ms_per_mult": round(pms, 4)}
+        log("plain: %.3f ms per multiply, %.1f ct-mults/s" % (pms, 1e3 / pms))
+
+    bytes_per_mult = mult_bytes(N, k, level, K, prm.alpha, jobs)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(log_n, L, K, dnum, k, level)
+    rec = {
+        "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "ct-mults/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(float(step_ms.mean()), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "%d-input multiply, N=2^%d, %d+%d primes, dnum=%d, level %d, batch %d"
+                               % (k, log_n, L, K, dnum, level, jobs),
+                   "k": k, "log_n": log_n, "level": level, "batch": jobs, "parallelism": "none"},
+        "plain": plain,
+        "batched_over_plain": round(value / plain["value"], 3) if plain else None,
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
+                       "p99": round(float(np.percentile(step_ms, 99)), 4), "of": "one batched step"},
+        "hbm_frac_whole_path": round(value * bytes_per_mult / 1e9 / HBM_PEAK_GBS, 5),
+        "algorithmic_bytes_per_mult": int(bytes_per_mult),
+        "roofline": rl,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

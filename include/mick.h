@@ -197,6 +197,16 @@ int mick_mul_relin_rescale_batch(const mick_params* prm, const mick_keys* keys, 
  * Exposed for testing and benchmarking of the transform itself. */
 int mick_ntt(const mick_params* prm, uint32_t* data_dev, int n_limbs, int first_prime, int inverse, void* stream);
 
+/* ---------------------------------------------------------------- instrumentation
+ * Not part of the paper's method: timing support for benchmarks.  While
+ * enabled, every kernel launch of the library is bracketed by a pair of HIP
+ * events recorded on the launch's stream (process-wide switch). */
+int mick_profile_enable(int on);
+/* Waits for the recorded events, then returns the number of launch sites
+ * seen (at most `max`) with, per site, a static name, the summed kernel time
+ * in milliseconds and the number of launches; clears the records. */
+int mick_profile_collect(int max, const char** names, double* total_ms, int* launches);
+
 #ifdef __cplusplus
 }
 #endif

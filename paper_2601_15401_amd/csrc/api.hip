@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,38 @@ int set_error(int status, const std::string& msg) {
 int hip_error(hipError_t e, const char* what) {
   if (e == hipSuccess) return MICK_OK;
   return set_error(MICK_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- profiler
+namespace {
+const char* const kSiteNames[P_COUNT] = {
+    "tensor",       "intt_d.passA",  "intt_d.passB",  "modup_bconv", "ntt_modup.passA", "ntt_modup.passB",
+    "kip",          "intt_acc.passA", "intt_acc.passB", "moddown_rescale", "ntt_out.passA", "ntt_out.passB",
+    "rescale_sums", "rescale_combine", "ntt_other.passA", "ntt_other.passB"};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<hipEvent_t> g_prof_events;            // pool, two per record
+std::vector<std::pair<int, int>> g_prof_records;  // (site, first event index)
+}  // namespace
+
+ProfScope::ProfScope(int site_, hipStream_t s) : site(site_), idx(-1), stream(s) {
+  if (!g_prof_on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  size_t need = 2 * (g_prof_records.size() + 1);
+  while (g_prof_events.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    g_prof_events.push_back(e);
+  }
+  idx = (int)(2 * g_prof_records.size());
+  g_prof_records.push_back({site, idx});
+  (void)hipEventRecord(g_prof_events[idx], s);
+}
+
+ProfScope::~ProfScope() {
+  if (idx < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  (void)hipEventRecord(g_prof_events[idx + 1], stream);
 }
 
 }  // namespace mick
@@ -159,8 +192,9 @@ int build_tables(mick_params* prm) {
   prm->dt.nfix = prm->dt.itw + n_tw;
   prm->dt.rpow = prm->dt.nfix + n_fix;
 
-  // ---- ModUp tables per (level, digit)
-  const int a = prm->alpha;
+  // ---- ModUp tables per (level, digit), rows padded with zeros to the
+  // kernel's digit width
+  const int a = prm->alpha, arows = modup_rows(a);
   std::vector<uint32_t> mu;
   prm->modup_off.assign((size_t)L * prm->dnum, 0);
   for (int level = 1; level <= L; level++) {
@@ -170,7 +204,7 @@ int build_tables(mick_params* prm) {
       prm->modup_off[(size_t)(level - 1) * prm->dnum + b] = mu.size();
       if (lo >= hi) continue;
       int cnt = hi - lo;
-      std::vector<uint32_t> qh(cnt), qhs(cnt);
+      std::vector<uint32_t> qh(arows, 0), qhs(arows, 0), C((size_t)arows * El, 0);
       for (int j = 0; j < cnt; j++) {
         uint32_t qj = prm->q[lo + j];
         uint64_t x = 1;
@@ -178,18 +212,17 @@ int build_tables(mick_params* prm) {
           if (i != j) x = x * invmod(prm->q[lo + i] % qj, qj) % qj;
         qh[j] = (uint32_t)x;
         qhs[j] = shoup_companion((uint32_t)x, qj);
+        for (int e = 0; e < El; e++) {
+          uint32_t me = e < level ? prm->q[e] : prm->p[e - level];
+          uint64_t y = 1;
+          for (int i = 0; i < cnt; i++)
+            if (i != j) y = y * (prm->q[lo + i] % me) % me;
+          C[(size_t)j * El + e] = (uint32_t)y;
+        }
       }
       mu.insert(mu.end(), qh.begin(), qh.end());
       mu.insert(mu.end(), qhs.begin(), qhs.end());
-      for (int j = 0; j < cnt; j++) {
-        for (int e = 0; e < El; e++) {
-          uint32_t me = e < level ? prm->q[e] : prm->p[e - level];
-          uint64_t x = 1;
-          for (int i = 0; i < cnt; i++)
-            if (i != j) x = x * (prm->q[lo + i] % me) % me;
-          mu.push_back((uint32_t)x);
-        }
-      }
+      mu.insert(mu.end(), C.begin(), C.end());
     }
   }
   MICK_TRY(dev_alloc(&prm->d_modup, mu.size()));
@@ -300,7 +333,8 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
   // ModUp: INTT of d_2..d_k
   LimbMap m = simple_map(prm, 0, level);
   m.job_stride = (long long)job_stride;
-  MICK_TRY(ntt_launch(prm, ws + lay.D + 2 * (size_t)level * N, ws + lay.dcoef, m, (k - 1) * level, n_jobs, true, s));
+  MICK_TRY(ntt_launch(prm, ws + lay.D + 2 * (size_t)level * N, ws + lay.dcoef, m, (k - 1) * level, n_jobs, true, s,
+                      P_INTT_D));
   // basis conversion from each digit
   ModupArgs ma{};
   ma.tab = prm->d_modup;
@@ -325,7 +359,7 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
   mx.skip_alpha = prm->alpha;
   mx.skip_level = level;
   mx.job_stride = (long long)job_stride;
-  MICK_TRY(ntt_launch(prm, ws + lay.X, ws + lay.X, mx, (k - 1) * B * E, n_jobs, false, s));
+  MICK_TRY(ntt_launch(prm, ws + lay.X, ws + lay.X, mx, (k - 1) * B * E, n_jobs, false, s, P_NTT_X));
   // key inner product, combined over t, with D_l added on the q rows
   KipArgs ka{};
   ka.log_n = prm->log_n;
@@ -348,7 +382,7 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
   ma2.off_lo = 0;
   ma2.off_hi = L - level;
   ma2.job_stride = (long long)job_stride;
-  MICK_TRY(ntt_launch(prm, ws + lay.acc, ws + lay.acc, ma2, 2 * E, n_jobs, true, s));
+  MICK_TRY(ntt_launch(prm, ws + lay.acc, ws + lay.acc, ma2, 2 * E, n_jobs, true, s, P_INTT_ACC));
   // scaled BConv, subtraction and the combined rescale, then the final NTT
   MdArgs A = md_args(prm, level, mu);
   A.acc_job = (long long)job_stride;
@@ -356,7 +390,7 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
   MICK_TRY(launch_moddown_rs(prm, ws + lay.acc, out, A, mu, n_jobs, s));
   LimbMap mo = simple_map(prm, 0, level - mu);
   mo.job_stride = (long long)out_job;
-  MICK_TRY(ntt_launch(prm, out, out, mo, 2 * (level - mu), n_jobs, false, s));
+  MICK_TRY(ntt_launch(prm, out, out, mo, 2 * (level - mu), n_jobs, false, s, P_NTT_OUT));
   return MICK_OK;
 }
 
@@ -760,6 +794,36 @@ int mick_mul_relin_rescale_batch(const mick_params* prm, const mick_keys* keys, 
   MICK_TRY(launch_tensor(prm, in, (long long)(k * ct_elems), k, level, w + lay.D, (long long)lay.total, n_jobs, s));
   const size_t out_job = 2 * (size_t)(level - k + 1) * N;
   return relin_rescale_ws(prm, keys, k, level, k - 1, w, lay.total, n_jobs, outs_dev, out_job, s);
+}
+
+int mick_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return MICK_OK;
+}
+
+int mick_profile_collect(int max, const char** names, double* total_ms, int* launches) {
+  if (max < 0 || (max > 0 && (!names || !total_ms || !launches))) return set_error(MICK_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double ms[P_COUNT] = {0};
+  int cnt[P_COUNT] = {0};
+  for (auto& r : g_prof_records) {
+    MICK_HIP(hipEventSynchronize(g_prof_events[r.second + 1]), "profile sync");
+    float t = 0;
+    MICK_HIP(hipEventElapsedTime(&t, g_prof_events[r.second], g_prof_events[r.second + 1]), "profile elapsed");
+    ms[r.first] += t;
+    cnt[r.first]++;
+  }
+  g_prof_records.clear();
+  int n = 0;
+  for (int i = 0; i < P_COUNT && n < max; i++) {
+    if (!cnt[i]) continue;
+    names[n] = kSiteNames[i];
+    total_ms[n] = ms[i];
+    launches[n] = cnt[i];
+    n++;
+  }
+  return n;
 }
 
 int mick_ntt(const mick_params* prm, uint32_t* data_dev, int n_limbs, int first_prime, int inverse, void* stream) {

@@ -77,13 +77,44 @@ struct mick_keys {
 
 namespace mick {
 
+// Launch sites the optional profiler distinguishes.  A transform site's
+// pass A is the listed value, its pass B the next one.
+enum ProfSite {
+  P_TENSOR,
+  P_INTT_D,
+  P_INTT_D_B,
+  P_MODUP,
+  P_NTT_X,
+  P_NTT_X_B,
+  P_KIP,
+  P_INTT_ACC,
+  P_INTT_ACC_B,
+  P_MODDOWN_RS,
+  P_NTT_OUT,
+  P_NTT_OUT_B,
+  P_RS_SUMS,
+  P_RS_COMBINE,
+  P_OTHER,
+  P_OTHER_B,
+  P_COUNT
+};
+
+// Records a pair of HIP events around one launch on `s` when profiling is
+// enabled (mick_profile_enable); free otherwise.
+struct ProfScope {
+  ProfScope(int site, hipStream_t s);
+  ~ProfScope();
+  int site, idx;
+  hipStream_t stream;
+};
+
 // Error reporting (thread-local message).
 int set_error(int status, const std::string& msg);
 int hip_error(hipError_t e, const char* what);
 
 // Transforms (ntt.hip).  src may equal dst.
 int ntt_launch(const mick_params* prm, const uint32_t* src, uint32_t* dst, const LimbMap& map, int n_limbs, int n_jobs,
-               bool inverse, hipStream_t s);
+               bool inverse, hipStream_t s, int site = P_OTHER);
 LimbMap simple_map(const mick_params* prm, int first_prime, int n_limbs);
 
 inline size_t evk_offset(const mick_params* prm, int t, int b, int l) {

@@ -6,6 +6,11 @@ namespace mick {
 
 constexpr int kMaxAlpha = 8;  // primes per key-switching digit
 constexpr int kMaxKp = 8;     // special primes p_i
+constexpr int kMaxE = 68;     // extended basis: 60 ciphertext primes + 8 special primes
+
+// Rows of the ModUp table for a digit width alpha: the kernels are built for
+// alpha in {1, 2, 4, 8} and read zero-padded rows up to that width.
+inline int modup_rows(int alpha) { return alpha <= 2 ? alpha : (alpha <= 4 ? 4 : 8); }
 
 struct CtPtrs {
   const uint32_t* p[kMaxK];

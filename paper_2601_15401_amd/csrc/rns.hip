@@ -76,38 +76,59 @@ __global__ __launch_bounds__(kThreads) void k_tensor(CtPtrs in, long long in_job
 // eq. (basis conversion): for digit b of the active primes, y_j =
 // [x_j qhat_j^-1]_{q_j}, then [sum_j y_j qhat_j]_m for every other modulus m
 // of the extended basis.  Input coefficient domain, output coefficient
-// domain (the NTT follows).  Table of (level, digit):
-//   [a] qhat_j^-1, [a] Shoup companions, [a][E] qhat_j mod m_e.
+// domain (the NTT follows).  Table of (level, digit), padded to ALPHA rows
+// with zeros when the digit is truncated at this level:
+//   [ALPHA] qhat_j^-1, [ALPHA] Shoup companions, [ALPHA][E] qhat_j mod m_e.
+// The table and the targets' reduction constants are staged in LDS; each
+// thread converts 4 neighbouring coefficients.
+template <int ALPHA>
 __global__ __launch_bounds__(kThreads) void k_modup(const uint32_t* dcoef, uint32_t* X, ModupArgs A, DevTables T) {
+  __shared__ uint32_t s_c[ALPHA * kMaxE];
+  __shared__ Red64 s_red[kMaxE];
   const size_t N = (size_t)1 << A.log_n;
-  const size_t n = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const size_t n = ((size_t)blockIdx.x * kThreads + threadIdx.x) * 4;
   const int tb = blockIdx.y;  // (t - 2) * B + b
   const int t2 = tb / A.B, b = tb - t2 * A.B;
   const int lo = b * A.alpha;
   const int a = min(A.alpha, A.level - lo);
   const uint32_t* tab = A.tab + A.tab_off[b];
-  const uint32_t* C = tab + 2 * a;
+  const int E = A.E;
+  for (int i = threadIdx.x; i < ALPHA * E; i += kThreads) s_c[i] = tab[2 * ALPHA + i];
+  for (int e = threadIdx.x; e < E; e += kThreads) s_red[e] = T.red[e < A.level ? e : A.L + (e - A.level)];
   const size_t job = (size_t)blockIdx.z;
   const uint32_t* src = dcoef + job * (size_t)A.dcoef_job + ((size_t)t2 * A.level + lo) * N + n;
-  uint32_t* dst = X + job * (size_t)A.x_job + ((size_t)tb * A.E) * N + n;
-  uint32_t y[kMaxAlpha];
+  uint32_t* dst = X + job * (size_t)A.x_job + ((size_t)tb * E) * N + n;
+  uint4 y[ALPHA];
 #pragma unroll
-  for (int j = 0; j < kMaxAlpha; j++) {
-    if (j < a) {
-      const uint32_t qj = T.mod[lo + j];
-      y[j] = shoup(src[(size_t)j * N], tab[j], tab[a + j], qj);
-    }
+  for (int j = 0; j < ALPHA; j++) {
+    const int row = min(j, a - 1);  // padded rows read a valid limb, scaled by 0
+    const uint32_t qj = T.mod[lo + row];
+    const uint4 v = *reinterpret_cast<const uint4*>(src + (size_t)row * N);
+    const uint32_t w = tab[j], wsh = tab[ALPHA + j];
+    y[j].x = shoup(v.x, w, wsh, qj);
+    y[j].y = shoup(v.y, w, wsh, qj);
+    y[j].z = shoup(v.z, w, wsh, qj);
+    y[j].w = shoup(v.w, w, wsh, qj);
   }
-  for (int e = 0; e < A.E; e++) {
+  __syncthreads();
+  for (int e = 0; e < E; e++) {
     if (e >= lo && e < lo + a) continue;
-    const int pe = e < A.level ? e : A.L + (e - A.level);
-    const Red64 rc = T.red[pe];
-    uint64_t acc = 0;
+    const Red64 rc = s_red[e];
+    uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
-    for (int j = 0; j < kMaxAlpha; j++) {
-      if (j < a) acc += (uint64_t)y[j] * C[(size_t)j * A.E + e];
+    for (int j = 0; j < ALPHA; j++) {
+      const uint64_t c = s_c[j * E + e];
+      s0 += y[j].x * c;
+      s1 += y[j].y * c;
+      s2 += y[j].z * c;
+      s3 += y[j].w * c;
     }
-    dst[(size_t)e * N] = reduce64(acc, rc);
+    uint4 o;
+    o.x = reduce64(s0, rc);
+    o.y = reduce64(s1, rc);
+    o.z = reduce64(s2, rc);
+    o.w = reduce64(s3, rc);
+    *reinterpret_cast<uint4*>(dst + (size_t)e * N) = o;
   }
 }
 
@@ -368,6 +389,7 @@ int launch_tensor(const mick_params* prm, const CtPtrs& in, long long in_job_str
   dim3 grid((unsigned)(prm->N / (kThreads * 4)), (unsigned)level, (unsigned)n_jobs);
   const DevTables& T = prm->dt;
   const int ln = prm->log_n;
+  ProfScope ps(P_TENSOR, s);
   switch (k) {
 #define MICK_T(KK) \
   case KK: k_tensor<KK><<<grid, kThreads, 0, s>>>(in, in_job_stride, level, ln, D, d_job_stride, T); break;
@@ -380,14 +402,23 @@ int launch_tensor(const mick_params* prm, const CtPtrs& in, long long in_job_str
 
 int launch_modup(const mick_params* prm, const uint32_t* dcoef, uint32_t* X, const ModupArgs& A, int k, int n_jobs,
                  hipStream_t s) {
-  dim3 grid((unsigned)(prm->N / kThreads), (unsigned)((k - 1) * A.B), (unsigned)n_jobs);
-  k_modup<<<grid, kThreads, 0, s>>>(dcoef, X, A, prm->dt);
+  dim3 grid((unsigned)(prm->N / (kThreads * 4)), (unsigned)((k - 1) * A.B), (unsigned)n_jobs);
+  ProfScope ps(P_MODUP, s);
+  if (A.E > kMaxE) return set_error(MICK_E_ARG, "extended basis too large");
+  switch (A.alpha) {
+    case 1: k_modup<1><<<grid, kThreads, 0, s>>>(dcoef, X, A, prm->dt); break;
+    case 2: k_modup<2><<<grid, kThreads, 0, s>>>(dcoef, X, A, prm->dt); break;
+    case 3:
+    case 4: k_modup<4><<<grid, kThreads, 0, s>>>(dcoef, X, A, prm->dt); break;
+    default: k_modup<8><<<grid, kThreads, 0, s>>>(dcoef, X, A, prm->dt); break;
+  }
   return hip_error(hipGetLastError(), "modup launch");
 }
 
 int launch_kip(const mick_params* prm, const uint32_t* D, const uint32_t* X, const uint32_t* evk, uint32_t* acc,
                const KipArgs& A, hipStream_t s) {
   const DevTables& T = prm->dt;
+  ProfScope ps(P_KIP, s);
   if (A.n_jobs <= 1) {
     dim3 grid((unsigned)(prm->N / kThreads), (unsigned)A.E, 1);
     k_kip<1><<<grid, kThreads, 0, s>>>(D, X, evk, acc, A, T);
@@ -402,6 +433,7 @@ int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out
                       hipStream_t s) {
   dim3 grid((unsigned)(prm->N / kThreads), 2, (unsigned)n_jobs);
   const DevTables& T = prm->dt;
+  ProfScope ps(P_MODDOWN_RS, s);
   switch (mu) {
 #define MICK_M(MM) \
   case MM: k_moddown_rs<MM><<<grid, kThreads, 0, s>>>(acc, out, A, T); break;
@@ -417,6 +449,7 @@ int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout,
                    hipStream_t s) {
   dim3 grid((unsigned)(prm->N / kThreads), 2, 1);
   const DevTables& T = prm->dt;
+  ProfScope ps(P_RS_SUMS, s);
   switch (mu) {
 #define MICK_R(MM) \
   case MM: k_rs_sums<MM><<<grid, kThreads, 0, s>>>(topc, bout, A, T); break;
@@ -431,6 +464,7 @@ int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout,
 int launch_rs_combine(const mick_params* prm, const uint32_t* Ain, const uint32_t* Bn, uint32_t* out, const MdArgs& A,
                       int mu, hipStream_t s) {
   dim3 grid((unsigned)(prm->N / kThreads), (unsigned)(A.level - mu), 2);
+  ProfScope ps(P_RS_COMBINE, s);
   k_rs_combine<<<grid, kThreads, 0, s>>>(Ain, Bn, out, A, mu, prm->dt);
   return hip_error(hipGetLastError(), "rescale combine launch");
 }

@@ -51,6 +51,9 @@ _SIGS = {
     "mick_mul_relin_rescale_batch": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
                                                     _vp, ctypes.c_size_t, _vp]),
     "mick_ntt": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "mick_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "mick_profile_collect": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
 }
 
 _lib = None
@@ -283,3 +286,20 @@ def ntt(prm: Params, data: torch.Tensor, first_prime: int, inverse: bool = False
     """In-place transform of data [n_limbs, N]; limb i uses prime index first_prime + i."""
     _check(load().mick_ntt(prm.handle, _ptr(data), data.shape[0], first_prime, int(inverse), _stream()), "mick_ntt")
     return data
+
+
+def profile_enable(on: bool = True):
+    """Bracket every library kernel launch with HIP events on its stream."""
+    _check(load().mick_profile_enable(int(on)), "mick_profile_enable")
+
+
+def profile_collect():
+    """{site: (total_ms, launches)} for the launches recorded since the last collect."""
+    n_max = 32
+    names = (ctypes.c_char_p * n_max)()
+    ms = (ctypes.c_double * n_max)()
+    cnt = (ctypes.c_int * n_max)()
+    n = load().mick_profile_collect(n_max, names, ms, cnt)
+    if n < 0:
+        raise MickError(n, "mick_profile_collect")
+    return {names[i].decode(): (ms[i], cnt[i]) for i in range(n)}
