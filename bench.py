@@ -58,9 +58,17 @@ def site_work(site, N, k, level, K, alpha, jobs):
     limb = 4.0 * N
     new_limbs = (k - 1) * (B * E - level)  # ModUp outputs that are transformed
     bfly = 9.0
-    if site.startswith("ntt_modup"):
-        n = jobs * new_limbs
-        return 2 * limb * n, n * (N / 2) * 8 * bfly
+    if site == "modup_bconv_passA":
+        # reads the d_t limbs once, writes pass-A outputs of the new limbs
+        n_in, n_out = jobs * (k - 1) * level, jobs * new_limbs
+        return limb * (n_in + n_out), jobs * new_limbs * (N * (2 * alpha + 12.0) + (N / 2) * 8 * bfly)
+    if site == "passB_kip":
+        # reads pass-A outputs, the digits' own d_t, d_0 and d_1, the keys once per
+        # batch; writes the two accumulators
+        x = jobs * (new_limbs + (k - 1) * level)
+        keys = (k - 1) * B * 2 * E
+        return limb * (x + keys + jobs * 2 * level + jobs * 2 * E), \
+            jobs * (new_limbs * (N / 2) * 8 * bfly + (k - 1) * B * E * N * 2 * 9.0)
     if site.startswith("intt_d"):
         n = jobs * (k - 1) * level
         return 2 * limb * n, n * (N / 2) * 8 * bfly
@@ -73,13 +81,6 @@ def site_work(site, N, k, level, K, alpha, jobs):
     if site == "tensor":
         n_in, n_out = jobs * k * 2 * level, jobs * (k + 1) * level
         return limb * (n_in + n_out), jobs * level * N * (k * (k + 1) - 2) * 7.0
-    if site == "modup_bconv":
-        n_in, n_out = jobs * (k - 1) * level, jobs * new_limbs
-        return limb * (n_in + n_out), jobs * new_limbs * N * (2 * alpha + 10.0)
-    if site == "kip":
-        x = jobs * (k - 1) * B * E
-        keys = math.ceil(jobs / 8) * (k - 1) * B * 2 * E
-        return limb * (x + keys + jobs * 2 * level + jobs * 2 * E), jobs * (k - 1) * B * E * N * 2 * 2.0
     if site == "moddown_rescale":
         return limb * jobs * (2 * E + 2 * (level - mu)), jobs * 2 * (level - mu) * N * (2 * (K + mu) + 30.0)
     return 0.0, 0.0

@@ -31,8 +31,8 @@ int hip_error(hipError_t e, const char* what) {
 // ---------------------------------------------------------------- profiler
 namespace {
 const char* const kSiteNames[P_COUNT] = {
-    "tensor",       "intt_d.passA",  "intt_d.passB",  "modup_bconv", "ntt_modup.passA", "ntt_modup.passB",
-    "kip",          "intt_acc.passA", "intt_acc.passB", "moddown_rescale", "ntt_out.passA", "ntt_out.passB",
+    "tensor",       "intt_d.passA",  "intt_d.passB",  "modup_bconv_passA", "unused.passA", "unused.passB",
+    "passB_kip",    "intt_acc.passA", "intt_acc.passB", "moddown_rescale", "ntt_out.passA", "ntt_out.passB",
     "rescale_sums", "rescale_combine", "ntt_other.passA", "ntt_other.passB"};
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -228,6 +228,29 @@ int build_tables(mick_params* prm) {
   MICK_TRY(dev_alloc(&prm->d_modup, mu.size()));
   MICK_HIP(hipMemcpy(prm->d_modup, mu.data(), mu.size() * 4, hipMemcpyHostToDevice), "modup upload");
 
+  // ---- per level: the inverse transform's N^-1 constants times qhat_j^-1
+  // of limb j within its digit (the scaling step of eq. (basis conversion))
+  std::vector<uint32_t> ds;
+  prm->dscale_off.assign((size_t)L + 1, 0);
+  for (int level = 1; level <= L; level++) {
+    prm->dscale_off[level] = ds.size();
+    for (int j = 0; j < level; j++) {
+      const int lo = (j / a) * a, hi = std::min(lo + a, level);
+      const uint32_t qj = prm->q[j];
+      uint64_t sc = 1;
+      for (int i = lo; i < hi; i++)
+        if (i != j) sc = sc * invmod(prm->q[i] % qj, qj) % qj;
+      const uint32_t* nf = h_fix + 4 * (size_t)j;
+      const uint32_t f0 = (uint32_t)(nf[0] * sc % qj), f2 = (uint32_t)(nf[2] * sc % qj);
+      ds.push_back(f0);
+      ds.push_back(shoup_companion(f0, qj));
+      ds.push_back(f2);
+      ds.push_back(shoup_companion(f2, qj));
+    }
+  }
+  MICK_TRY(dev_alloc(&prm->d_dscale, ds.size()));
+  MICK_HIP(hipMemcpy(prm->d_dscale, ds.data(), ds.size() * 4, hipMemcpyHostToDevice), "dscale upload");
+
   // ---- ModDown tables and the chain constants q_d^-1 mod q_t
   std::vector<uint32_t> md;
   for (int i = 0; i < K; i++) {
@@ -330,12 +353,13 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
                      size_t job_stride, int n_jobs, uint32_t* out, size_t out_job, hipStream_t s) {
   const Layout lay = mul_layout(prm, k, level);
   const int N = prm->N, L = prm->L, K = prm->K, E = level + K, B = digits_at(prm, level);
-  // ModUp: INTT of d_2..d_k
+  // ModUp: INTT of d_2..d_k, each limb also multiplied by its qhat_j^-1
   LimbMap m = simple_map(prm, 0, level);
   m.job_stride = (long long)job_stride;
+  m.nfix_pos = prm->d_dscale + prm->dscale_off[level];
   MICK_TRY(ntt_launch(prm, ws + lay.D + 2 * (size_t)level * N, ws + lay.dcoef, m, (k - 1) * level, n_jobs, true, s,
                       P_INTT_D));
-  // basis conversion from each digit
+  // basis conversion from each digit fused with pass A of the new limbs' NTT
   ModupArgs ma{};
   ma.tab = prm->d_modup;
   for (int b = 0; b < B; b++) ma.tab_off[b] = (int)prm->modup_off[(size_t)(level - 1) * prm->dnum + b];
@@ -345,22 +369,12 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
   ma.E = E;
   ma.B = B;
   ma.alpha = prm->alpha;
+  ma.groups = (k - 1) * B;
   ma.dcoef_job = (long long)job_stride;
   ma.x_job = (long long)job_stride;
-  MICK_TRY(launch_modup(prm, ws + lay.dcoef, ws + lay.X, ma, k, n_jobs, s));
-  // NTT of the converted limbs (the digit's own limbs are skipped)
-  LimbMap mx{};
-  mx.period = E;
-  mx.group_stride = (long long)E * N;
-  mx.split = level;
-  mx.off_lo = 0;
-  mx.off_hi = L - level;
-  mx.skip_groups = B;
-  mx.skip_alpha = prm->alpha;
-  mx.skip_level = level;
-  mx.job_stride = (long long)job_stride;
-  MICK_TRY(ntt_launch(prm, ws + lay.X, ws + lay.X, mx, (k - 1) * B * E, n_jobs, false, s, P_NTT_X));
-  // key inner product, combined over t, with D_l added on the q rows
+  MICK_TRY(launch_modup_a(prm, ws + lay.dcoef, ws + lay.X, ma, n_jobs, s));
+  // pass B fused with the key inner product, combined over t, with D_l added
+  // on the q rows
   KipArgs ka{};
   ka.log_n = prm->log_n;
   ka.level = level;
@@ -373,13 +387,10 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
   ka.n_jobs = n_jobs;
   ka.key_poly = (long long)(L + K) * N;
   ka.d_job = ka.x_job = ka.acc_job = (long long)job_stride;
-  MICK_TRY(launch_kip(prm, ws + lay.D, ws + lay.X, keys->d_evk, ws + lay.acc, ka, s));
+  MICK_TRY(launch_kip_b(prm, ws + lay.X, ws + lay.D, keys->d_evk, ws + lay.acc, ka, s));
   // relocated ModDown: INTT of every accumulator limb
-  LimbMap ma2{};
-  ma2.period = E;
-  ma2.group_stride = (long long)E * N;
+  LimbMap ma2 = simple_map(prm, 0, E);
   ma2.split = level;
-  ma2.off_lo = 0;
   ma2.off_hi = L - level;
   ma2.job_stride = (long long)job_stride;
   MICK_TRY(ntt_launch(prm, ws + lay.acc, ws + lay.acc, ma2, 2 * E, n_jobs, true, s, P_INTT_ACC));
@@ -456,6 +467,7 @@ void mick_params_destroy(mick_params* prm) {
   if (prm->d_modup) (void)hipFree(prm->d_modup);
   if (prm->d_moddown) (void)hipFree(prm->d_moddown);
   if (prm->d_rescale) (void)hipFree(prm->d_rescale);
+  if (prm->d_dscale) (void)hipFree(prm->d_dscale);
   delete prm;
 }
 
@@ -532,7 +544,10 @@ int mick_keygen(const mick_params* prm, uint64_t seed, int k_max, void* stream, 
         for (int r = 0; r < E; r++) {
           uint32_t m = prm->mods[r];
           uint32_t g = (r < L && r >= lo && r < hi) ? prm->p_mod_q[r] : 0;
-          uint32_t f = r < L ? prm->pinv_q[r] : 1;
+          // device copy: q rows times [P^-1] (Sec. IV), every row times
+          // R = 2^32 (Montgomery form for the key inner product)
+          const uint64_t R = ((uint64_t)1 << 32) % m;
+          uint32_t f = (uint32_t)((r < L ? prm->pinv_q[r] : 1) * R % m);
           hrow[4 * r + 0] = g;
           hrow[4 * r + 1] = f;
           hrow[4 * r + 2] = shoup_companion(f, m);
@@ -588,10 +603,12 @@ int mick_keys_export(const mick_keys* keys, int what, int t, int b, void* host_o
              "export evk");
     MICK_HIP(hipStreamSynchronize(s), "export sync");
     for (int l = 0; l < 2; l++)
-      for (int r = 0; r < L; r++) {  // undo the [P^-1] of the q rows
-        uint64_t P = prm->p_mod_q[r], m = prm->q[r];
+      for (int r = 0; r < E; r++) {  // undo the [P^-1] of the q rows and the factor R
+        const uint64_t m = prm->mods[r];
+        const uint64_t Rinv = invmod(((uint64_t)1 << 32) % m, m);
+        const uint64_t f = (r < L ? prm->p_mod_q[r] : 1) * Rinv % m;
         uint32_t* row = o + ((size_t)l * E + r) * N;
-        for (size_t i = 0; i < N; i++) row[i] = (uint32_t)(row[i] * P % m);
+        for (size_t i = 0; i < N; i++) row[i] = (uint32_t)(row[i] * f % m);
       }
     return MICK_OK;
   }

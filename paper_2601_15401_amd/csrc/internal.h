@@ -28,15 +28,16 @@ struct DevTables {
 
 // Where the limbs of one transform launch live and which prime each uses.
 // Limb i: group g = i / period, position pos = i % period; data at
-// base + g * group_stride + pos * N; prime pos + off_lo if pos < split, else
-// pos + off_hi.  With skip_groups > 0 the group cycles over that many digits
-// and positions inside the digit's own primes are skipped (ModUp outputs).
+// base + g * group_stride + pos * N (+ blockIdx.z * job_stride); prime
+// pos + off_lo if pos < split, else pos + off_hi.  nfix_pos, when set,
+// replaces the per-prime N^-1 constants of an inverse transform by
+// per-position ones (4 words each), folding a per-limb factor into it.
 struct LimbMap {
   int period;
   long long group_stride;
   int split, off_lo, off_hi;
-  int skip_groups, skip_alpha, skip_level;
-  long long job_stride;  // elements between jobs (blockIdx.z)
+  long long job_stride;
+  const uint32_t* nfix_pos;
 };
 
 struct mick_params_impl;
@@ -57,6 +58,10 @@ struct mick_params {
   uint32_t* d_moddown = nullptr;
   // rescale tables per (level, mu)
   uint32_t* d_rescale = nullptr;
+  // per level: N^-1 constants of the ModUp inverse transform with each limb's
+  // qhat_j^-1 (within its digit) folded in, [level][4]
+  uint32_t* d_dscale = nullptr;
+  std::vector<size_t> dscale_off;  // index level
   std::vector<size_t> rescale_off;  // index level * (L + 1) + mu
   // P^-1 and P mod q_j (host)
   std::vector<uint32_t> pinv_q, p_mod_q;

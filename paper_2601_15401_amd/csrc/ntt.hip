@@ -1,4 +1,5 @@
-// Negacyclic NTT / INTT for N = 2^13 .. 2^16 on gfx950.
+// Negacyclic NTT / INTT for N = 2^13 .. 2^16 on gfx950, and the two fused
+// kernels of the ModUp path that are built on the same transform passes.
 //
 // The transform is the merged-twiddle Cooley-Tukey factorisation of
 // NTT(a)[k] = a(psi^(2 brv(k) + 1)): stage s (s = 0 .. log N - 1) splits the
@@ -27,7 +28,20 @@
 // below 2^30 use Harvey's lazy butterflies (values kept below 4q); the
 // 31-bit special primes keep values below 2q with one more conditional
 // subtraction per butterfly.  The last pass stores canonical residues.
+//
+// ModUp fusion (Sec. II ModUp, Sec. III combined key products):
+//  * k_modup_a: the fast basis conversion of eq. (basis conversion) computed
+//    while loading pass A of the forward transform of each new limb, so the
+//    converted limbs are never written in the coefficient domain.  The input
+//    limbs already carry the factor qhat_j^-1 (merged into the inverse
+//    transform that produced them).
+//  * k_kip_b: pass B of those forward transforms fused with the key inner
+//    product: one workgroup owns one tile of one extended-basis limb and
+//    accumulates sum_t sum_b X_{t,b} ek'_{t,b,l} over every (t, b) pair in
+//    registers, reusing the limb's pass-B twiddles for all pairs; the
+//    transformed limbs are never written.
 #include "internal.h"
+#include "rns.h"
 
 namespace mick {
 
@@ -36,20 +50,51 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTileLog = 13;
 
-template <bool MODUP>
-__device__ __forceinline__ void resolve(const LimbMap& mp, int limb, int log_n, int& prime, size_t& off, bool& skip) {
-  int g = limb / mp.period;
-  int pos = limb - g * mp.period;
-  prime = pos < mp.split ? pos + mp.off_lo : pos + mp.off_hi;
-  off = (size_t)g * (size_t)mp.group_stride + ((size_t)pos << log_n) + (size_t)blockIdx.z * (size_t)mp.job_stride;
-  skip = false;
-  if constexpr (MODUP) {
-    int b = g % mp.skip_groups;
-    int lo = b * mp.skip_alpha;
-    int hi = min(lo + mp.skip_alpha, mp.skip_level);
-    skip = pos >= lo && pos < hi;
+template <int LOGR>
+struct Geo {
+  static constexpr int LOGC = kTileLog - LOGR;
+  static constexpr int COLS = 1 << LOGC;
+  static constexpr int PAD = COLS + 1;
+  static constexpr int RB0 = (LOGR == 6) ? 3 : 4;
+  static constexpr int RB1 = LOGR - RB0;
+  static constexpr int LDS_WORDS = (1 << LOGR) * PAD;
+};
+
+// Item layout of one round.  An item is one column c and 2^RB rows
+// rbase + j 2^NLO_LOG, j < 2^RB.
+template <int LOGR, bool PASSB, bool STRIDED, int NT = kThreads>
+struct Rnd {
+  using G = Geo<LOGR>;
+  static constexpr int RB = STRIDED ? G::RB0 : G::RB1;
+  static constexpr int E = 1 << RB;
+  static constexpr int SL0 = STRIDED ? 0 : G::RB0;  // first local stage of the round
+  static constexpr int NLO_LOG = STRIDED ? LOGR - G::RB0 : 0;
+  static constexpr int ITEMS = (1 << kTileLog) >> RB;
+  static constexpr int NI = ITEMS / NT;  // items per thread
+  // pass B's strided round walks the rows of a column with consecutive lanes
+  static constexpr bool LO_FAST = PASSB && STRIDED;
+  // pass B's consecutive round moves 2^RB neighbouring words per lane
+  static constexpr bool VEC = PASSB && !STRIDED;
+
+  __device__ static void decode(int it, int& c, int& rbase, int& hi) {
+    int lo;
+    if constexpr (LO_FAST) {
+      lo = it & ((1 << NLO_LOG) - 1);
+      c = it >> NLO_LOG;
+      hi = 0;
+    } else {
+      c = it & (G::COLS - 1);
+      const int hl = it >> G::LOGC;
+      lo = STRIDED ? hl : 0;
+      hi = STRIDED ? 0 : hl;
+    }
+    rbase = (hi << (LOGR - SL0)) + lo;
   }
-}
+  __device__ static int row(int rbase, int j) { return rbase + (j << NLO_LOG); }
+  __device__ static size_t gidx(int H, int col, int r) {
+    return PASSB ? ((size_t)col << LOGR) + r : ((size_t)r << H) + col;
+  }
+};
 
 // Forward (Cooley-Tukey) butterfly.
 template <bool LAZY>
@@ -82,7 +127,8 @@ __device__ __forceinline__ void gs(uint32_t& x, uint32_t& y, uint2 w, uint32_t q
   }
 }
 
-// The last inverse stage with N^-1 merged into both outputs.
+// The last inverse stage with N^-1 (times a per-limb factor) merged into both
+// outputs: nf = (f, f', w1 f, (w1 f)').
 template <bool LAZY>
 __device__ __forceinline__ void gs_last(uint32_t& x, uint32_t& y, const uint4& nf, uint32_t q) {
   if constexpr (LAZY) {
@@ -102,188 +148,358 @@ __device__ __forceinline__ uint32_t canonical(uint32_t v, uint32_t q) {
   return red1(v, q);
 }
 
-// One round of a pass.  STRIDED: the pass's first RB0 stages; otherwise its
-// last RB1 stages.  Loads from global memory when FROM_G, else from LDS;
-// stores to global memory when TO_G, else to LDS.
-template <int LOGR, bool FWD, bool LAZY, bool PASSB, bool STRIDED, bool FROM_G, bool TO_G>
-__device__ __forceinline__ void nround(const uint32_t* gsrc, uint32_t* gdst,
-                                       uint32_t* lds, int s0, int H, int col0, uint32_t q,
-                                       const uint2* __restrict__ tw, const uint4& nfix) {
-  constexpr int LOGC = kTileLog - LOGR;
-  constexpr int COLS = 1 << LOGC;
-  constexpr int PAD = COLS + 1;
-  constexpr int RB0 = (LOGR == 6) ? 3 : 4;
-  constexpr int RB = STRIDED ? RB0 : LOGR - RB0;
+// Butterflies of one item: loads the round's twiddles (stage u of the round
+// uses 2^u of them), then runs the RB stages in order (forward) or reverse
+// order (inverse).  HAS_STAGE0: the round contains global stage 0 of an
+// inverse transform, which takes nfix instead of a twiddle.
+template <int RB, bool FWD, bool LAZY, bool HAS_STAGE0>
+__device__ __forceinline__ void item_bfly(uint32_t (&x)[1 << RB], const uint2* __restrict__ tw, int s_first, int s0,
+                                          int hi, int blk, uint32_t q, const uint4& nfix) {
   constexpr int E = 1 << RB;
-  constexpr int SL0 = STRIDED ? 0 : RB0;          // first local stage of the round
-  constexpr int NLO_LOG = STRIDED ? LOGR - RB0 : 0;
-  constexpr int NLO = 1 << NLO_LOG;
-  constexpr int ITEMS = (1 << kTileLog) >> RB;
-  // pass B's strided round walks the rows of a column with consecutive lanes
-  constexpr bool LO_FAST = PASSB && STRIDED;
-  constexpr bool FINAL = FWD ? PASSB : !PASSB;     // last pass of the transform
-  constexpr bool STORE_FINAL = FINAL && TO_G;
-  constexpr bool HAS_STAGE0 = !FWD && !PASSB && STRIDED;  // global stage 0 (inverse)
-  constexpr bool VEC = PASSB && !STRIDED;           // 16 neighbouring words per lane
-
+  uint2 w[E];
 #pragma unroll
-  for (int it0 = 0; it0 < ITEMS; it0 += kThreads) {
-    const int it = it0 + threadIdx.x;
-    int c, lo, hi;
-    if constexpr (LO_FAST) {
-      lo = it & (NLO - 1);
-      c = it >> NLO_LOG;
-      hi = 0;
-    } else {
-      c = it & (COLS - 1);
-      const int hl = it >> LOGC;
-      lo = STRIDED ? hl : 0;
-      hi = STRIDED ? 0 : hl;
-    }
-    const int rbase = (hi << (LOGR - SL0)) + lo;
-    const int col = col0 + c;
-    const int blk = PASSB ? col : 0;
-    uint32_t x[E];
-    // ---- load
-    if constexpr (FROM_G && VEC) {
+  for (int u = 0; u < RB; u++) {
+    if (HAS_STAGE0 && u == 0) continue;
+    const int s = s_first + u;
 #pragma unroll
-      for (int j = 0; j < E; j += 4) {
-        const uint4 v = *reinterpret_cast<const uint4*>(gsrc + ((size_t)col << LOGR) + rbase + j);
-        x[j] = v.x;
-        x[j + 1] = v.y;
-        x[j + 2] = v.z;
-        x[j + 3] = v.w;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < E; j++) {
-        const int r = rbase + (j << NLO_LOG);
-        if constexpr (FROM_G) {
-          const size_t g = PASSB ? ((size_t)col << LOGR) + r : ((size_t)r << H) + col;
-          x[j] = gsrc[g];
-        } else {
-          x[j] = lds[r * PAD + c];
-        }
-      }
-    }
-    // ---- the round's twiddles: stage u uses 2^u of them, w[2^u + g]
-    uint2 w[E];
+    for (int g = 0; g < (1 << u); g++) w[(1 << u) + g] = tw[(1 << s) + ((((hi << u) + g)) << s0) + blk];
+  }
+  if constexpr (FWD) {
 #pragma unroll
     for (int u = 0; u < RB; u++) {
-      if (HAS_STAGE0 && u == 0) continue;
-      const int s = s0 + SL0 + u;
-#pragma unroll
-      for (int g = 0; g < (1 << u); g++) {
-        const int rr = (hi << u) + g;
-        w[(1 << u) + g] = tw[(1 << s) + (rr << s0) + blk];
-      }
-    }
-    // ---- butterflies
-    if constexpr (FWD) {
-#pragma unroll
-      for (int u = 0; u < RB; u++) {
-        const int half = 1 << (RB - 1 - u);
-#pragma unroll
-        for (int j = 0; j < E; j++) {
-          if (j & half) continue;
-          ct<LAZY>(x[j], x[j + half], w[(1 << u) + (j >> (RB - u))], q);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int u = RB - 1; u >= 0; u--) {
-        const int half = 1 << (RB - 1 - u);
-#pragma unroll
-        for (int j = 0; j < E; j++) {
-          if (j & half) continue;
-          if (HAS_STAGE0 && u == 0)
-            gs_last<LAZY>(x[j], x[j + half], nfix, q);
-          else
-            gs<LAZY>(x[j], x[j + half], w[(1 << u) + (j >> (RB - u))], q);
-        }
-      }
-    }
-    // ---- store
-    if constexpr (STORE_FINAL) {
-#pragma unroll
-      for (int j = 0; j < E; j++) x[j] = canonical<FWD, LAZY>(x[j], q);
-    }
-    if constexpr (TO_G && VEC) {
-#pragma unroll
-      for (int j = 0; j < E; j += 4) {
-        uint4 o;
-        o.x = x[j];
-        o.y = x[j + 1];
-        o.z = x[j + 2];
-        o.w = x[j + 3];
-        *reinterpret_cast<uint4*>(gdst + ((size_t)col << LOGR) + rbase + j) = o;
-      }
-    } else {
+      const int half = 1 << (RB - 1 - u);
 #pragma unroll
       for (int j = 0; j < E; j++) {
-        const int r = rbase + (j << NLO_LOG);
-        if constexpr (TO_G) {
-          const size_t g = PASSB ? ((size_t)col << LOGR) + r : ((size_t)r << H) + col;
-          gdst[g] = x[j];
-        } else {
-          lds[r * PAD + c] = x[j];
-        }
+        if (j & half) continue;
+        ct<LAZY>(x[j], x[j + half], w[(1 << u) + (j >> (RB - u))], q);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = RB - 1; u >= 0; u--) {
+      const int half = 1 << (RB - 1 - u);
+#pragma unroll
+      for (int j = 0; j < E; j++) {
+        if (j & half) continue;
+        if (HAS_STAGE0 && u == 0)
+          gs_last<LAZY>(x[j], x[j + half], nfix, q);
+        else
+          gs<LAZY>(x[j], x[j + half], w[(1 << u) + (j >> (RB - u))], q);
       }
     }
   }
 }
 
+template <typename RD>
+__device__ __forceinline__ void load_global(uint32_t (&x)[RD::E], const uint32_t* g, int H, int col, int rbase) {
+  if constexpr (RD::VEC) {
+#pragma unroll
+    for (int j = 0; j < RD::E; j += 4) {
+      const uint4 v = *reinterpret_cast<const uint4*>(g + RD::gidx(H, col, rbase + j));
+      x[j] = v.x;
+      x[j + 1] = v.y;
+      x[j + 2] = v.z;
+      x[j + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < RD::E; j++) x[j] = g[RD::gidx(H, col, RD::row(rbase, j))];
+  }
+}
+
+template <typename RD>
+__device__ __forceinline__ void store_global(const uint32_t (&x)[RD::E], uint32_t* g, int H, int col, int rbase) {
+  if constexpr (RD::VEC) {
+#pragma unroll
+    for (int j = 0; j < RD::E; j += 4) {
+      uint4 o;
+      o.x = x[j];
+      o.y = x[j + 1];
+      o.z = x[j + 2];
+      o.w = x[j + 3];
+      *reinterpret_cast<uint4*>(g + RD::gidx(H, col, rbase + j)) = o;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < RD::E; j++) g[RD::gidx(H, col, RD::row(rbase, j))] = x[j];
+  }
+}
+
+template <typename RD, int PAD>
+__device__ __forceinline__ void load_lds(uint32_t (&x)[RD::E], const uint32_t* lds, int c, int rbase) {
+#pragma unroll
+  for (int j = 0; j < RD::E; j++) x[j] = lds[RD::row(rbase, j) * PAD + c];
+}
+
+template <typename RD, int PAD>
+__device__ __forceinline__ void store_lds(const uint32_t (&x)[RD::E], uint32_t* lds, int c, int rbase) {
+#pragma unroll
+  for (int j = 0; j < RD::E; j++) lds[RD::row(rbase, j) * PAD + c] = x[j];
+}
+
+// ------------------------------------------------------------------ plain transform pass
+
 template <int LOGR, bool FWD, bool LAZY, bool PASSB>
 __device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, uint32_t* lds, int s0, int H, int col0,
                                           uint32_t q, const uint2* tw, const uint4& nfix) {
+  using G = Geo<LOGR>;
   // forward: strided round first; inverse: consecutive round first
-  nround<LOGR, FWD, LAZY, PASSB, FWD, true, false>(src, dst, lds, s0, H, col0, q, tw, nfix);
+  using R1 = Rnd<LOGR, PASSB, FWD>;
+  using R2 = Rnd<LOGR, PASSB, !FWD>;
+  constexpr bool FINAL = FWD ? PASSB : !PASSB;  // last pass of the transform
+#pragma unroll
+  for (int i = 0; i < R1::NI; i++) {
+    int c, rb, hi;
+    R1::decode(i * kThreads + threadIdx.x, c, rb, hi);
+    uint32_t x[R1::E];
+    load_global<R1>(x, src, H, col0 + c, rb);
+    item_bfly<R1::RB, FWD, LAZY, false>(x, tw, s0 + R1::SL0, s0, hi, PASSB ? col0 + c : 0, q, nfix);
+    store_lds<R1, G::PAD>(x, lds, c, rb);
+  }
   __syncthreads();
-  nround<LOGR, FWD, LAZY, PASSB, !FWD, false, true>(src, dst, lds, s0, H, col0, q, tw, nfix);
+#pragma unroll
+  for (int i = 0; i < R2::NI; i++) {
+    int c, rb, hi;
+    R2::decode(i * kThreads + threadIdx.x, c, rb, hi);
+    uint32_t x[R2::E];
+    load_lds<R2, G::PAD>(x, lds, c, rb);
+    // the inverse's strided round of pass A holds global stage 0
+    item_bfly<R2::RB, FWD, LAZY, !FWD && !PASSB>(x, tw, s0 + R2::SL0, s0, hi, PASSB ? col0 + c : 0, q, nfix);
+    if constexpr (FINAL) {
+#pragma unroll
+      for (int j = 0; j < R2::E; j++) x[j] = canonical<FWD, LAZY>(x[j], q);
+    }
+    store_global<R2>(x, dst, H, col0 + c, rb);
+  }
 }
 
-// MODUP: the launch transforms ModUp outputs, whose limbs inside the digit's
-// own primes are skipped.  PASSB selects the pass (pass A has s0 = 0).
-template <int LOGR, bool FWD, bool MODUP, bool PASSB>
+// Launch index y -> limb: group g = y / period, position pos = y % period.
+__device__ __forceinline__ void resolve(const LimbMap& mp, int limb, int log_n, int& prime, int& pos, size_t& off) {
+  const int g = limb / mp.period;
+  pos = limb - g * mp.period;
+  prime = pos < mp.split ? pos + mp.off_lo : pos + mp.off_hi;
+  off = (size_t)g * (size_t)mp.group_stride + ((size_t)pos << log_n) + (size_t)blockIdx.z * (size_t)mp.job_stride;
+}
+
+template <int LOGR, bool FWD, bool PASSB>
 __global__ __launch_bounds__(kThreads) void k_ntt_pass(const uint32_t* src, uint32_t* dst, LimbMap mp, DevTables T,
                                                        int log_n, int s0) {
-  constexpr int LOGC = kTileLog - LOGR;
-  constexpr int COLS = 1 << LOGC;
-  __shared__ uint32_t lds[(1 << LOGR) * (COLS + 1)];
-  int prime;
+  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  int prime, pos;
   size_t off;
-  bool skip;
-  resolve<MODUP>(mp, blockIdx.y, log_n, prime, off, skip);
-  if (skip) return;
+  resolve(mp, blockIdx.y, log_n, prime, pos, off);
   const uint32_t q = T.mod[prime];
   const uint2* tw = reinterpret_cast<const uint2*>(FWD ? T.tw : T.itw) + ((size_t)prime << log_n);
-  const uint4 nfix = reinterpret_cast<const uint4*>(T.nfix)[prime];
+  const uint4 nfix = mp.nfix_pos ? reinterpret_cast<const uint4*>(mp.nfix_pos)[pos]
+                                 : reinterpret_cast<const uint4*>(T.nfix)[prime];
   const int H = log_n - s0 - LOGR;  // > 0 in pass A, 0 in pass B
-  const int col0 = blockIdx.x * COLS;
+  const int col0 = blockIdx.x * Geo<LOGR>::COLS;
   if (q < (1u << 30))
     pass_body<LOGR, FWD, true, PASSB>(src + off, dst + off, lds, s0, H, col0, q, tw, nfix);
   else
     pass_body<LOGR, FWD, false, PASSB>(src + off, dst + off, lds, s0, H, col0, q, tw, nfix);
 }
 
-template <bool FWD, bool MODUP, bool PASSB>
-void launch_pass_t(int logr, dim3 grid, hipStream_t s, const uint32_t* src, uint32_t* dst, const LimbMap& mp,
-                   const DevTables& T, int log_n, int s0) {
-  switch (logr) {
-    case 6: k_ntt_pass<6, FWD, MODUP, PASSB><<<grid, kThreads, 0, s>>>(src, dst, mp, T, log_n, s0); break;
-    case 7: k_ntt_pass<7, FWD, MODUP, PASSB><<<grid, kThreads, 0, s>>>(src, dst, mp, T, log_n, s0); break;
-    default: k_ntt_pass<8, FWD, MODUP, PASSB><<<grid, kThreads, 0, s>>>(src, dst, mp, T, log_n, s0); break;
-  }
-}
-
 template <bool FWD, bool PASSB>
 void launch_pass(int logr, dim3 grid, hipStream_t s, const uint32_t* src, uint32_t* dst, const LimbMap& mp,
                  const DevTables& T, int log_n, int s0, int site) {
   ProfScope ps(site, s);
-  if (mp.skip_groups > 0)
-    launch_pass_t<FWD, true, PASSB>(logr, grid, s, src, dst, mp, T, log_n, s0);
+  switch (logr) {
+    case 6: k_ntt_pass<6, FWD, PASSB><<<grid, kThreads, 0, s>>>(src, dst, mp, T, log_n, s0); break;
+    case 7: k_ntt_pass<7, FWD, PASSB><<<grid, kThreads, 0, s>>>(src, dst, mp, T, log_n, s0); break;
+    default: k_ntt_pass<8, FWD, PASSB><<<grid, kThreads, 0, s>>>(src, dst, mp, T, log_n, s0); break;
+  }
+}
+
+// ------------------------------------------------------------------ ModUp: conversion + pass A
+
+// Workgroup order: the targets of one source tile run back to back on one
+// XCD (block b goes to XCD b % 8), so the source tile is read from L2.
+template <int LOGR, int ALPHA, bool LAZY>
+__device__ __forceinline__ void modup_a_body(const uint32_t* const (&srow)[ALPHA], const uint32_t (&cc)[ALPHA],
+                                             const Red64& rc, uint32_t* dst, uint32_t* lds, int H, int col0,
+                                             uint32_t q, const uint2* tw) {
+  using G = Geo<LOGR>;
+  using R1 = Rnd<LOGR, false, true>;
+  using R2 = Rnd<LOGR, false, false>;
+  const uint4 nf{};
+#pragma unroll
+  for (int i = 0; i < R1::NI; i++) {
+    int c, rb, hi;
+    R1::decode(i * kThreads + threadIdx.x, c, rb, hi);
+    uint32_t x[R1::E];
+#pragma unroll
+    for (int j = 0; j < R1::E; j++) {
+      const size_t g = R1::gidx(H, col0 + c, R1::row(rb, j));
+      uint64_t acc = 0;
+#pragma unroll
+      for (int a = 0; a < ALPHA; a++) acc += (uint64_t)srow[a][g] * cc[a];
+      x[j] = reduce64(acc, rc);
+    }
+    item_bfly<R1::RB, true, LAZY, false>(x, tw, R1::SL0, 0, hi, 0, q, nf);
+    store_lds<R1, G::PAD>(x, lds, c, rb);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < R2::NI; i++) {
+    int c, rb, hi;
+    R2::decode(i * kThreads + threadIdx.x, c, rb, hi);
+    uint32_t x[R2::E];
+    load_lds<R2, G::PAD>(x, lds, c, rb);
+    item_bfly<R2::RB, true, LAZY, false>(x, tw, R2::SL0, 0, hi, 0, q, nf);
+    store_global<R2>(x, dst, H, col0 + c, rb);
+  }
+}
+
+template <int LOGR, int ALPHA>
+__global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint32_t* X, ModupArgs A, DevTables T) {
+  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
+  const int e = seq % A.E;
+  const int unit = (seq / A.E) * 8 + xcd;  // (job, t, b, tile)
+  if (unit >= A.units) return;
+  const int tile = unit % A.tiles;
+  const int src_grp = unit / A.tiles;
+  const int job = src_grp / A.groups;
+  const int tb = src_grp - job * A.groups;  // (t - 2) * B + b
+  const int t2 = tb / A.B, b = tb - t2 * A.B;
+  const int lo = b * A.alpha;
+  const int na = min(A.alpha, A.level - lo);
+  if (e >= lo && e < lo + na) return;  // the digit's own limbs are the input itself
+  const int pe = e < A.level ? e : A.L + (e - A.level);
+  const uint32_t q = T.mod[pe];
+  const Red64 rc = T.red[pe];
+  const uint2* tw = reinterpret_cast<const uint2*>(T.tw) + ((size_t)pe << A.log_n);
+  const size_t N = (size_t)1 << A.log_n;
+  const uint32_t* C = A.tab + A.tab_off[b] + 2 * ALPHA;  // [ALPHA][E] qhat_j mod m_e, zero rows padded
+  const uint32_t* base = dsc + (size_t)job * (size_t)A.dcoef_job + ((size_t)t2 * A.level + lo) * N;
+  const uint32_t* srow[ALPHA];
+  uint32_t cc[ALPHA];
+#pragma unroll
+  for (int a = 0; a < ALPHA; a++) {
+    srow[a] = base + (size_t)min(a, na - 1) * N;  // padded rows read a valid limb, times 0
+    cc[a] = C[a * A.E + e];
+  }
+  uint32_t* dst = X + (size_t)job * (size_t)A.x_job + ((size_t)tb * A.E + e) * N;
+  const int H = A.log_n - LOGR;
+  const int col0 = tile * Geo<LOGR>::COLS;
+  if (q < (1u << 30))
+    modup_a_body<LOGR, ALPHA, true>(srow, cc, rc, dst, lds, H, col0, q, tw);
   else
-    launch_pass_t<FWD, false, PASSB>(logr, grid, s, src, dst, mp, T, log_n, s0);
+    modup_a_body<LOGR, ALPHA, false>(srow, cc, rc, dst, lds, H, col0, q, tw);
+}
+
+// ------------------------------------------------------------------ pass B + key inner product
+
+constexpr int kKipThreads = 512;
+
+template <int LOGR, bool LAZY>
+__device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* De, const uint32_t* evk_e,
+                                           uint32_t* acc_e, const KipArgs& A, uint32_t* lds, int e, int col0,
+                                           uint32_t q, uint32_t minv, const uint2* tw) {
+  using G = Geo<LOGR>;
+  using R1 = Rnd<LOGR, true, true, kKipThreads>;
+  using R2 = Rnd<LOGR, true, false, kKipThreads>;
+  const size_t N = (size_t)1 << A.log_n;
+  const int s0 = A.log_n - LOGR;
+  const uint4 nf{};
+  uint32_t a0[R2::NI][R2::E], a1[R2::NI][R2::E];
+#pragma unroll
+  for (int i = 0; i < R2::NI; i++)
+#pragma unroll
+    for (int j = 0; j < R2::E; j++) a0[i][j] = a1[i][j] = 0;
+  for (int t = 2; t <= A.k; t++) {
+    for (int b = 0; b < A.B; b++) {
+      const int lo = b * A.alpha;
+      const bool own = e >= lo && e < min(lo + A.alpha, A.level);
+      const uint32_t* k0p = evk_e + (((size_t)(t - 2) * A.dnum + b) * 2) * (size_t)A.key_poly;
+      const uint32_t* k1p = k0p + A.key_poly;
+      if (!own) {
+        const uint32_t* src = Xe + (((size_t)(t - 2) * A.B + b) * A.E) * N;
+#pragma unroll
+        for (int i = 0; i < R1::NI; i++) {
+          int c, rb, hi;
+          R1::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+          uint32_t x[R1::E];
+          load_global<R1>(x, src, 0, col0 + c, rb);
+          item_bfly<R1::RB, true, LAZY, false>(x, tw, s0 + R1::SL0, s0, hi, col0 + c, q, nf);
+          store_lds<R1, G::PAD>(x, lds, c, rb);
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < R2::NI; i++) {
+        int c, rb, hi;
+        R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+        uint32_t x[R2::E];
+        if (own) {
+          load_global<R2>(x, De + (size_t)t * A.level * N, 0, col0 + c, rb);  // D_t, NTT domain
+        } else {
+          load_lds<R2, G::PAD>(x, lds, c, rb);
+          item_bfly<R2::RB, true, LAZY, false>(x, tw, s0 + R2::SL0, s0, hi, col0 + c, q, nf);
+        }
+        const size_t g = R2::gidx(0, col0 + c, rb);
+#pragma unroll
+        for (int j = 0; j < R2::E; j += 4) {
+          const uint4 k0 = *reinterpret_cast<const uint4*>(k0p + g + j);
+          const uint4 k1 = *reinterpret_cast<const uint4*>(k1p + g + j);
+          a0[i][j] = add_mod(a0[i][j], mont_mul(x[j], k0.x, q, minv), q);
+          a0[i][j + 1] = add_mod(a0[i][j + 1], mont_mul(x[j + 1], k0.y, q, minv), q);
+          a0[i][j + 2] = add_mod(a0[i][j + 2], mont_mul(x[j + 2], k0.z, q, minv), q);
+          a0[i][j + 3] = add_mod(a0[i][j + 3], mont_mul(x[j + 3], k0.w, q, minv), q);
+          a1[i][j] = add_mod(a1[i][j], mont_mul(x[j], k1.x, q, minv), q);
+          a1[i][j + 1] = add_mod(a1[i][j + 1], mont_mul(x[j + 1], k1.y, q, minv), q);
+          a1[i][j + 2] = add_mod(a1[i][j + 2], mont_mul(x[j + 2], k1.z, q, minv), q);
+          a1[i][j + 3] = add_mod(a1[i][j + 3], mont_mul(x[j + 3], k1.w, q, minv), q);
+        }
+      }
+      if (!own) __syncthreads();  // the next pair's first round rewrites the tile
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R2::NI; i++) {
+    int c, rb, hi;
+    R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+    if (e < A.level) {  // relocated ModDown input D_l + P^-1 C~ on the q rows
+      uint32_t d0[R2::E], d1[R2::E];
+      load_global<R2>(d0, De, 0, col0 + c, rb);
+      load_global<R2>(d1, De + (size_t)A.level * N, 0, col0 + c, rb);
+#pragma unroll
+      for (int j = 0; j < R2::E; j++) {
+        a0[i][j] = add_mod(a0[i][j], d0[j], q);
+        a1[i][j] = add_mod(a1[i][j], d1[j], q);
+      }
+    }
+    store_global<R2>(a0[i], acc_e, 0, col0 + c, rb);
+    store_global<R2>(a1[i], acc_e + (size_t)A.E * N, 0, col0 + c, rb);
+  }
+}
+
+// Workgroup order: the jobs of one (limb, tile) run back to back on one XCD,
+// so the key tiles they share are read from L2.
+template <int LOGR>
+__global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const uint32_t* D, const uint32_t* evk,
+                                                       uint32_t* acc, KipArgs A, DevTables T) {
+  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
+  const int job = seq % A.n_jobs;
+  const int unit = (seq / A.n_jobs) * 8 + xcd;  // (limb e, tile)
+  if (unit >= A.E * A.tiles) return;
+  const int e = unit / A.tiles;
+  const int tile = unit - e * A.tiles;
+  const int pe = e < A.level ? e : A.L + (e - A.level);
+  const uint32_t q = T.mod[pe], minv = T.minv[pe];
+  const uint2* tw = reinterpret_cast<const uint2*>(T.tw) + ((size_t)pe << A.log_n);
+  const size_t N = (size_t)1 << A.log_n;
+  const uint32_t* Xe = X + (size_t)job * (size_t)A.x_job + (size_t)e * N;
+  const uint32_t* De = D + (size_t)job * (size_t)A.d_job + (size_t)e * N;
+  const uint32_t* evk_e = evk + (size_t)pe * N;
+  uint32_t* acc_e = acc + (size_t)job * (size_t)A.acc_job + (size_t)e * N;
+  const int col0 = tile * Geo<LOGR>::COLS;
+  if (q < (1u << 30))
+    kip_b_body<LOGR, true>(Xe, De, evk_e, acc_e, A, lds, e, col0, q, minv, tw);
+  else
+    kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, e, col0, q, minv, tw);
 }
 
 }  // namespace
@@ -295,8 +511,8 @@ LimbMap simple_map(const mick_params* prm, int first_prime, int n_limbs) {
   m.split = n_limbs;
   m.off_lo = first_prime;
   m.off_hi = first_prime;
-  m.skip_groups = 0;
   m.job_stride = 0;
+  m.nfix_pos = nullptr;
   return m;
 }
 
@@ -315,6 +531,46 @@ int ntt_launch(const mick_params* prm, const uint32_t* src, uint32_t* dst, const
     launch_pass<false, false>(la, grid, s, dst, dst, map, prm->dt, log_n, 0, site);
   }
   return hip_error(hipGetLastError(), "ntt launch");
+}
+
+int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, ModupArgs A, int n_jobs, hipStream_t s) {
+  A.tiles = 1 << (prm->log_n - kTileLog);
+  A.units = n_jobs * A.groups * A.tiles;
+  const unsigned blocks = (unsigned)(((A.units + 7) / 8) * 8 * A.E);
+  ProfScope ps(P_MODUP, s);
+  const int la = prm->split_a;
+  const DevTables& T = prm->dt;
+#define MICK_MA(LR, AL) k_modup_a<LR, AL><<<blocks, kThreads, 0, s>>>(dsc, X, A, T)
+#define MICK_MA_A(LR)                      \
+  switch (modup_rows(A.alpha)) {           \
+    case 1: MICK_MA(LR, 1); break;         \
+    case 2: MICK_MA(LR, 2); break;         \
+    case 4: MICK_MA(LR, 4); break;         \
+    default: MICK_MA(LR, 8); break;        \
+  }
+  if (la == 7) {
+    MICK_MA_A(7)
+  } else {
+    MICK_MA_A(8)
+  }
+#undef MICK_MA_A
+#undef MICK_MA
+  return hip_error(hipGetLastError(), "modup launch");
+}
+
+int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,
+                 KipArgs A, hipStream_t s) {
+  A.tiles = 1 << (prm->log_n - kTileLog);
+  const int units = A.E * A.tiles;
+  const unsigned blocks = (unsigned)(((units + 7) / 8) * 8 * A.n_jobs);
+  ProfScope ps(P_KIP, s);
+  const DevTables& T = prm->dt;
+  switch (prm->split_b) {
+    case 6: k_kip_b<6><<<blocks, kKipThreads, 0, s>>>(X, D, evk, acc, A, T); break;
+    case 7: k_kip_b<7><<<blocks, kKipThreads, 0, s>>>(X, D, evk, acc, A, T); break;
+    default: k_kip_b<8><<<blocks, kKipThreads, 0, s>>>(X, D, evk, acc, A, T); break;
+  }
+  return hip_error(hipGetLastError(), "kip launch");
 }
 
 }  // namespace mick

@@ -17,14 +17,17 @@ struct CtPtrs {
 };
 
 struct ModupArgs {
-  const uint32_t* tab;  // modup table block of this level
-  int tab_off[16];      // per digit offset inside `tab`
+  const uint32_t* tab;  // ModUp tables
+  int tab_off[16];      // per digit offset of this level's table inside `tab`
   int log_n, level, L, E, B, alpha;
+  int groups;           // (k - 1) B source groups per job
+  int tiles, units;     // set by the launcher
   long long dcoef_job, x_job;
 };
 
 struct KipArgs {
   int log_n, level, L, E, B, alpha, dnum, k, n_jobs;
+  int tiles;           // set by the launcher
   long long key_poly;  // elements per key polynomial ((L+K) N)
   long long d_job, x_job, acc_job;
 };
@@ -39,10 +42,13 @@ struct MdArgs {
 
 int launch_tensor(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level, uint32_t* D,
                   long long d_job_stride, int n_jobs, hipStream_t s);
-int launch_modup(const mick_params* prm, const uint32_t* dcoef, uint32_t* X, const ModupArgs& A, int k, int n_jobs,
-                 hipStream_t s);
-int launch_kip(const mick_params* prm, const uint32_t* D, const uint32_t* X, const uint32_t* evk, uint32_t* acc,
-               const KipArgs& A, hipStream_t s);
+// ModUp basis conversion fused with pass A of the forward transform of the
+// new limbs (ntt.hip).  dsc: the d_t limbs in the coefficient domain, each
+// already multiplied by its qhat_j^-1.
+int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, ModupArgs A, int n_jobs, hipStream_t s);
+// Pass B of those transforms fused with the key inner product (ntt.hip).
+int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,
+                 KipArgs A, hipStream_t s);
 int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out, const MdArgs& A, int mu, int n_jobs,
                       hipStream_t s);
 int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout, const MdArgs& A, int mu,

@@ -1,7 +1,8 @@
-// Pointwise RNS kernels of the k-input multiply: tensor product, ModUp basis
-// conversion, key inner product, relocated ModDown fused with the combined
-// multi-level rescale, the steps of Algorithm 1, and the small pointwise
-// operations of key generation, encryption and decryption.
+// Pointwise RNS kernels of the k-input multiply: tensor product, relocated
+// ModDown fused with the combined multi-level rescale, the steps of
+// Algorithm 1, and the small pointwise operations of key generation,
+// encryption and decryption.  (The ModUp basis conversion and the key inner
+// product are fused into transform passes in ntt.hip.)
 #include "internal.h"
 #include "rns.h"
 
@@ -69,136 +70,6 @@ __global__ __launch_bounds__(kThreads) void k_tensor(CtPtrs in, long long in_job
     v.z = shoup(P[t].z, f, fsh, m);
     v.w = shoup(P[t].w, f, fsh, m);
     reinterpret_cast<uint4*>(out + (size_t)t * poly)[n] = v;
-  }
-}
-
-// ------------------------------------------------------------------ ModUp
-// eq. (basis conversion): for digit b of the active primes, y_j =
-// [x_j qhat_j^-1]_{q_j}, then [sum_j y_j qhat_j]_m for every other modulus m
-// of the extended basis.  Input coefficient domain, output coefficient
-// domain (the NTT follows).  Table of (level, digit), padded to ALPHA rows
-// with zeros when the digit is truncated at this level:
-//   [ALPHA] qhat_j^-1, [ALPHA] Shoup companions, [ALPHA][E] qhat_j mod m_e.
-// The table and the targets' reduction constants are staged in LDS; each
-// thread converts 4 neighbouring coefficients.
-template <int ALPHA>
-__global__ __launch_bounds__(kThreads) void k_modup(const uint32_t* dcoef, uint32_t* X, ModupArgs A, DevTables T) {
-  __shared__ uint32_t s_c[ALPHA * kMaxE];
-  __shared__ Red64 s_red[kMaxE];
-  const size_t N = (size_t)1 << A.log_n;
-  const size_t n = ((size_t)blockIdx.x * kThreads + threadIdx.x) * 4;
-  const int tb = blockIdx.y;  // (t - 2) * B + b
-  const int t2 = tb / A.B, b = tb - t2 * A.B;
-  const int lo = b * A.alpha;
-  const int a = min(A.alpha, A.level - lo);
-  const uint32_t* tab = A.tab + A.tab_off[b];
-  const int E = A.E;
-  for (int i = threadIdx.x; i < ALPHA * E; i += kThreads) s_c[i] = tab[2 * ALPHA + i];
-  for (int e = threadIdx.x; e < E; e += kThreads) s_red[e] = T.red[e < A.level ? e : A.L + (e - A.level)];
-  const size_t job = (size_t)blockIdx.z;
-  const uint32_t* src = dcoef + job * (size_t)A.dcoef_job + ((size_t)t2 * A.level + lo) * N + n;
-  uint32_t* dst = X + job * (size_t)A.x_job + ((size_t)tb * E) * N + n;
-  uint4 y[ALPHA];
-#pragma unroll
-  for (int j = 0; j < ALPHA; j++) {
-    const int row = min(j, a - 1);  // padded rows read a valid limb, scaled by 0
-    const uint32_t qj = T.mod[lo + row];
-    const uint4 v = *reinterpret_cast<const uint4*>(src + (size_t)row * N);
-    const uint32_t w = tab[j], wsh = tab[ALPHA + j];
-    y[j].x = shoup(v.x, w, wsh, qj);
-    y[j].y = shoup(v.y, w, wsh, qj);
-    y[j].z = shoup(v.z, w, wsh, qj);
-    y[j].w = shoup(v.w, w, wsh, qj);
-  }
-  __syncthreads();
-  for (int e = 0; e < E; e++) {
-    if (e >= lo && e < lo + a) continue;
-    const Red64 rc = s_red[e];
-    uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll
-    for (int j = 0; j < ALPHA; j++) {
-      const uint64_t c = s_c[j * E + e];
-      s0 += y[j].x * c;
-      s1 += y[j].y * c;
-      s2 += y[j].z * c;
-      s3 += y[j].w * c;
-    }
-    uint4 o;
-    o.x = reduce64(s0, rc);
-    o.y = reduce64(s1, rc);
-    o.z = reduce64(s2, rc);
-    o.w = reduce64(s3, rc);
-    *reinterpret_cast<uint4*>(dst + (size_t)e * N) = o;
-  }
-}
-
-// ------------------------------------------------------------------ key inner product
-// Acc_l[e] = sum_t sum_b X_{t,b}[e] ek'_{t,b,l}[e] over the extended basis,
-// X_{t,b}[e] = D_t[e] on the digit's own primes (Sec. III combined sum; the
-// q rows of ek' carry P^-1, Sec. IV).  On the q rows the relocated ModDown
-// input D_l + P^-1 C~ is formed here.  Up to JB jobs share each key load.
-template <int JB>
-__global__ __launch_bounds__(kThreads) void k_kip(const uint32_t* D, const uint32_t* X, const uint32_t* evk,
-                                                  uint32_t* acc, KipArgs A, DevTables T) {
-  const size_t N = (size_t)1 << A.log_n;
-  const size_t n = (size_t)blockIdx.x * kThreads + threadIdx.x;
-  const int e = blockIdx.y;
-  const int job0 = blockIdx.z * JB;
-  const int nj = min(JB, A.n_jobs - job0);
-  const int pe = e < A.level ? e : A.L + (e - A.level);
-  const Red64 rc = T.red[pe];
-  const int chunk = rc.m < (1u << 30) ? 16 : 4;  // products < m^2, sums stay below 2^64
-  const size_t key_row = ((size_t)pe << A.log_n) + n;
-  uint64_t a0[JB], a1[JB];
-  uint32_t r0[JB], r1[JB];
-#pragma unroll
-  for (int i = 0; i < JB; i++) {
-    a0[i] = a1[i] = 0;
-    r0[i] = r1[i] = 0;
-  }
-  int cnt = 0;
-  for (int t = 2; t <= A.k; t++) {
-    for (int b = 0; b < A.B; b++) {
-      const int lo = b * A.alpha;
-      const bool own = e >= lo && e < min(lo + A.alpha, A.level);
-      const size_t ko = (((size_t)(t - 2) * A.dnum + b) * 2) * A.key_poly;
-      const uint32_t k0 = evk[ko + key_row];
-      const uint32_t k1 = evk[ko + A.key_poly + key_row];
-#pragma unroll
-      for (int i = 0; i < JB; i++) {
-        if (i < nj) {
-          const size_t jo = (size_t)(job0 + i);
-          const uint32_t x = own ? D[jo * (size_t)A.d_job + ((size_t)t * A.level + e) * N + n]
-                                 : X[jo * (size_t)A.x_job + (((size_t)(t - 2) * A.B + b) * A.E + e) * N + n];
-          a0[i] += (uint64_t)x * k0;
-          a1[i] += (uint64_t)x * k1;
-        }
-      }
-      if (++cnt == chunk) {
-        cnt = 0;
-#pragma unroll
-        for (int i = 0; i < JB; i++) {
-          r0[i] = add_mod(r0[i], reduce64(a0[i], rc), rc.m);
-          r1[i] = add_mod(r1[i], reduce64(a1[i], rc), rc.m);
-          a0[i] = a1[i] = 0;
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < JB; i++) {
-    if (i < nj) {
-      const size_t jo = (size_t)(job0 + i);
-      uint32_t v0 = add_mod(r0[i], reduce64(a0[i], rc), rc.m);
-      uint32_t v1 = add_mod(r1[i], reduce64(a1[i], rc), rc.m);
-      if (e < A.level) {
-        v0 = add_mod(v0, D[jo * (size_t)A.d_job + (size_t)e * N + n], rc.m);
-        v1 = add_mod(v1, D[jo * (size_t)A.d_job + ((size_t)A.level + e) * N + n], rc.m);
-      }
-      uint32_t* o = acc + jo * (size_t)A.acc_job + (size_t)e * N + n;
-      o[0] = v0;
-      o[(size_t)A.E * N] = v1;
-    }
   }
 }
 
@@ -398,35 +269,6 @@ int launch_tensor(const mick_params* prm, const CtPtrs& in, long long in_job_str
     default: return set_error(MICK_E_ARG, "k out of range");
   }
   return hip_error(hipGetLastError(), "tensor launch");
-}
-
-int launch_modup(const mick_params* prm, const uint32_t* dcoef, uint32_t* X, const ModupArgs& A, int k, int n_jobs,
-                 hipStream_t s) {
-  dim3 grid((unsigned)(prm->N / (kThreads * 4)), (unsigned)((k - 1) * A.B), (unsigned)n_jobs);
-  ProfScope ps(P_MODUP, s);
-  if (A.E > kMaxE) return set_error(MICK_E_ARG, "extended basis too large");
-  switch (A.alpha) {
-    case 1: k_modup<1><<<grid, kThreads, 0, s>>>(dcoef, X, A, prm->dt); break;
-    case 2: k_modup<2><<<grid, kThreads, 0, s>>>(dcoef, X, A, prm->dt); break;
-    case 3:
-    case 4: k_modup<4><<<grid, kThreads, 0, s>>>(dcoef, X, A, prm->dt); break;
-    default: k_modup<8><<<grid, kThreads, 0, s>>>(dcoef, X, A, prm->dt); break;
-  }
-  return hip_error(hipGetLastError(), "modup launch");
-}
-
-int launch_kip(const mick_params* prm, const uint32_t* D, const uint32_t* X, const uint32_t* evk, uint32_t* acc,
-               const KipArgs& A, hipStream_t s) {
-  const DevTables& T = prm->dt;
-  ProfScope ps(P_KIP, s);
-  if (A.n_jobs <= 1) {
-    dim3 grid((unsigned)(prm->N / kThreads), (unsigned)A.E, 1);
-    k_kip<1><<<grid, kThreads, 0, s>>>(D, X, evk, acc, A, T);
-  } else {
-    dim3 grid((unsigned)(prm->N / kThreads), (unsigned)A.E, (unsigned)((A.n_jobs + 7) / 8));
-    k_kip<8><<<grid, kThreads, 0, s>>>(D, X, evk, acc, A, T);
-  }
-  return hip_error(hipGetLastError(), "kip launch");
 }
 
 int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out, const MdArgs& A, int mu, int n_jobs,
