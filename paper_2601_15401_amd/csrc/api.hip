@@ -212,9 +212,9 @@ int build_tables(mick_params* prm) {
           if (i != j) x = x * invmod(prm->q[lo + i] % qj, qj) % qj;
         qh[j] = (uint32_t)x;
         qhs[j] = shoup_companion((uint32_t)x, qj);
-        for (int e = 0; e < El; e++) {
+        for (int e = 0; e < El; e++) {  // qhat_j R mod m_e (Montgomery form)
           uint32_t me = e < level ? prm->q[e] : prm->p[e - level];
-          uint64_t y = 1;
+          uint64_t y = ((uint64_t)1 << 32) % me;
           for (int i = 0; i < cnt; i++)
             if (i != j) y = y * (prm->q[lo + i] % me) % me;
           C[(size_t)j * El + e] = (uint32_t)y;

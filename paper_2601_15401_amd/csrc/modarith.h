@@ -33,12 +33,23 @@ __device__ __forceinline__ uint32_t shoup(uint32_t y, uint32_t w, uint32_t wsh, 
 }
 
 // a * b * 2^-32 mod m in [0, m), for a * b < m * 2^32.  minv = m^-1 mod 2^32.
+// With lo = a b mod 2^32, a b - (lo minv mod 2^32) m is a multiple of 2^32
+// whose quotient r = hi - mh lies in (-m, m); min(r + m, r) (unsigned)
+// selects r + m exactly when r wrapped below zero.
 __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t m, uint32_t minv) {
-  uint64_t t = (uint64_t)a * b;
-  uint32_t lo = (uint32_t)t, hi = (uint32_t)(t >> 32);
-  uint32_t mh = __umulhi(lo * minv, m);
-  uint32_t r = hi - mh;
-  return hi < mh ? r + m : r;
+  const uint32_t lo = a * b, hi = __umulhi(a, b);
+  const uint32_t r = hi - __umulhi(lo * minv, m);
+  return min(r + m, r);
+}
+
+// Montgomery reduction of T < 2m 2^32: T 2^-32 mod m in [0, m).  The
+// quotient hi - mh lies in (-m, 2m) here; r + m would overflow 32 bits for
+// m near 2^31, so the negative case is detected by comparing hi and mh.
+__device__ __forceinline__ uint32_t redc_2m(uint64_t T, uint32_t m, uint32_t minv) {
+  const uint32_t lo = (uint32_t)T, hi = (uint32_t)(T >> 32);
+  const uint32_t mh = __umulhi(lo * minv, m);
+  const uint32_t r = hi - mh;
+  return hi < mh ? r + m : red1(r, m);
 }
 
 // Per-modulus constants for reducing a full 64-bit value.

@@ -91,8 +91,8 @@ struct Rnd {
     rbase = (hi << (LOGR - SL0)) + lo;
   }
   __device__ static int row(int rbase, int j) { return rbase + (j << NLO_LOG); }
-  __device__ static size_t gidx(int H, int col, int r) {
-    return PASSB ? ((size_t)col << LOGR) + r : ((size_t)r << H) + col;
+  __device__ static uint32_t gidx(int H, int col, int r) {  // < N <= 2^16
+    return PASSB ? ((uint32_t)col << LOGR) + r : ((uint32_t)r << H) + col;
   }
 };
 
@@ -148,21 +148,21 @@ __device__ __forceinline__ uint32_t canonical(uint32_t v, uint32_t q) {
   return red1(v, q);
 }
 
-// Butterflies of one item: loads the round's twiddles (stage u of the round
-// uses 2^u of them), then runs the RB stages in order (forward) or reverse
+// Butterflies of one item: fetches the round's twiddles (stage u of the
+// round uses 2^u of them; TW(s, rr) returns the twiddle of global stage s,
+// local block rr), then runs the RB stages in order (forward) or reverse
 // order (inverse).  HAS_STAGE0: the round contains global stage 0 of an
 // inverse transform, which takes nfix instead of a twiddle.
-template <int RB, bool FWD, bool LAZY, bool HAS_STAGE0>
-__device__ __forceinline__ void item_bfly(uint32_t (&x)[1 << RB], const uint2* __restrict__ tw, int s_first, int s0,
-                                          int hi, int blk, uint32_t q, const uint4& nfix) {
+template <int RB, bool FWD, bool LAZY, bool HAS_STAGE0, typename TW>
+__device__ __forceinline__ void item_bfly_t(uint32_t (&x)[1 << RB], const TW& twf, int s_first, int hi, uint32_t q,
+                                            const uint4& nfix) {
   constexpr int E = 1 << RB;
   uint2 w[E];
 #pragma unroll
   for (int u = 0; u < RB; u++) {
     if (HAS_STAGE0 && u == 0) continue;
-    const int s = s_first + u;
 #pragma unroll
-    for (int g = 0; g < (1 << u); g++) w[(1 << u) + g] = tw[(1 << s) + ((((hi << u) + g)) << s0) + blk];
+    for (int g = 0; g < (1 << u); g++) w[(1 << u) + g] = twf(s_first + u, u, (hi << u) + g);
   }
   if constexpr (FWD) {
 #pragma unroll
@@ -188,6 +188,19 @@ __device__ __forceinline__ void item_bfly(uint32_t (&x)[1 << RB], const uint2* _
       }
     }
   }
+}
+
+// Twiddles read from the per-prime table in global memory.
+struct TwGlobal {
+  const uint2* tw;
+  int s0, blk;
+  __device__ uint2 operator()(int s, int, int rr) const { return tw[(1 << s) + (rr << s0) + blk]; }
+};
+
+template <int RB, bool FWD, bool LAZY, bool HAS_STAGE0>
+__device__ __forceinline__ void item_bfly(uint32_t (&x)[1 << RB], const uint2* tw, int s_first, int s0, int hi,
+                                          int blk, uint32_t q, const uint4& nfix) {
+  item_bfly_t<RB, FWD, LAZY, HAS_STAGE0>(x, TwGlobal{tw, s0, blk}, s_first, hi, q, nfix);
 }
 
 template <typename RD>
@@ -315,9 +328,12 @@ void launch_pass(int logr, dim3 grid, hipStream_t s, const uint32_t* src, uint32
 
 // Workgroup order: the targets of one source tile run back to back on one
 // XCD (block b goes to XCD b % 8), so the source tile is read from L2.
+// The conversion constants carry a factor R = 2^32 (Montgomery form): the
+// sum of ALPHA <= 8 products of a residue below 2^30 and a constant below m
+// stays below 2m 2^32, so one Montgomery reduction returns it mod m.
 template <int LOGR, int ALPHA, bool LAZY>
 __device__ __forceinline__ void modup_a_body(const uint32_t* const (&srow)[ALPHA], const uint32_t (&cc)[ALPHA],
-                                             const Red64& rc, uint32_t* dst, uint32_t* lds, int H, int col0,
+                                             uint32_t minv, uint32_t* dst, uint32_t* lds, int H, int col0,
                                              uint32_t q, const uint2* tw) {
   using G = Geo<LOGR>;
   using R1 = Rnd<LOGR, false, true>;
@@ -330,11 +346,11 @@ __device__ __forceinline__ void modup_a_body(const uint32_t* const (&srow)[ALPHA
     uint32_t x[R1::E];
 #pragma unroll
     for (int j = 0; j < R1::E; j++) {
-      const size_t g = R1::gidx(H, col0 + c, R1::row(rb, j));
+      const uint32_t g = R1::gidx(H, col0 + c, R1::row(rb, j));
       uint64_t acc = 0;
 #pragma unroll
       for (int a = 0; a < ALPHA; a++) acc += (uint64_t)srow[a][g] * cc[a];
-      x[j] = reduce64(acc, rc);
+      x[j] = redc_2m(acc, q, minv);
     }
     item_bfly<R1::RB, true, LAZY, false>(x, tw, R1::SL0, 0, hi, 0, q, nf);
     store_lds<R1, G::PAD>(x, lds, c, rb);
@@ -367,11 +383,11 @@ __global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint3
   const int na = min(A.alpha, A.level - lo);
   if (e >= lo && e < lo + na) return;  // the digit's own limbs are the input itself
   const int pe = e < A.level ? e : A.L + (e - A.level);
-  const uint32_t q = T.mod[pe];
-  const Red64 rc = T.red[pe];
+  const uint32_t q = T.mod[pe], minv = T.minv[pe];
   const uint2* tw = reinterpret_cast<const uint2*>(T.tw) + ((size_t)pe << A.log_n);
   const size_t N = (size_t)1 << A.log_n;
-  const uint32_t* C = A.tab + A.tab_off[b] + 2 * ALPHA;  // [ALPHA][E] qhat_j mod m_e, zero rows padded
+  // [ALPHA][E] qhat_j R mod m_e, zero rows padded
+  const uint32_t* C = A.tab + A.tab_off[b] + 2 * ALPHA;
   const uint32_t* base = dsc + (size_t)job * (size_t)A.dcoef_job + ((size_t)t2 * A.level + lo) * N;
   const uint32_t* srow[ALPHA];
   uint32_t cc[ALPHA];
@@ -384,25 +400,46 @@ __global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint3
   const int H = A.log_n - LOGR;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    modup_a_body<LOGR, ALPHA, true>(srow, cc, rc, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, true>(srow, cc, minv, dst, lds, H, col0, q, tw);
   else
-    modup_a_body<LOGR, ALPHA, false>(srow, cc, rc, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, false>(srow, cc, minv, dst, lds, H, col0, q, tw);
 }
 
 // ------------------------------------------------------------------ pass B + key inner product
 
 constexpr int kKipThreads = 512;
 
+// The tile's pass-B twiddles staged in LDS: stage s0 + sl, block rr < 2^sl,
+// column c < COLS at COLS (2^sl - 1) + rr COLS + c.
+template <int COLS>
+struct TwLds {
+  const uint2* t;
+  int s0, c;
+  __device__ uint2 operator()(int s, int, int rr) const {
+    const int sl = s - s0;
+    return t[COLS * ((1 << sl) - 1) + rr * COLS + c];
+  }
+};
+
 template <int LOGR, bool LAZY>
 __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* De, const uint32_t* evk_e,
-                                           uint32_t* acc_e, const KipArgs& A, uint32_t* lds, int e, int col0,
-                                           uint32_t q, uint32_t minv, const uint2* tw) {
+                                           uint32_t* acc_e, const KipArgs& A, uint32_t* lds, uint2* ltw, int e,
+                                           int col0, uint32_t q, uint32_t minv, const uint2* tw) {
   using G = Geo<LOGR>;
   using R1 = Rnd<LOGR, true, true, kKipThreads>;
   using R2 = Rnd<LOGR, true, false, kKipThreads>;
   const size_t N = (size_t)1 << A.log_n;
   const int s0 = A.log_n - LOGR;
   const uint4 nf{};
+  // every (t, b) pair of this tile uses the same twiddles: stage them once
+  for (int i = threadIdx.x; i < G::COLS * ((1 << LOGR) - 1); i += kKipThreads) {
+    const int c = i & (G::COLS - 1);
+    const int k = i >> G::LOGC;  // (2^sl - 1) + rr
+    const int sl = 31 - __clz(k + 1);
+    const int rr = k + 1 - (1 << sl);
+    ltw[i] = tw[(1 << (s0 + sl)) + (rr << s0) + col0 + c];
+  }
+  __syncthreads();
   uint32_t a0[R2::NI][R2::E], a1[R2::NI][R2::E];
 #pragma unroll
   for (int i = 0; i < R2::NI; i++)
@@ -422,7 +459,7 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
           R1::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
           uint32_t x[R1::E];
           load_global<R1>(x, src, 0, col0 + c, rb);
-          item_bfly<R1::RB, true, LAZY, false>(x, tw, s0 + R1::SL0, s0, hi, col0 + c, q, nf);
+          item_bfly_t<R1::RB, true, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, c}, s0 + R1::SL0, hi, q, nf);
           store_lds<R1, G::PAD>(x, lds, c, rb);
         }
         __syncthreads();
@@ -436,9 +473,9 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
           load_global<R2>(x, De + (size_t)t * A.level * N, 0, col0 + c, rb);  // D_t, NTT domain
         } else {
           load_lds<R2, G::PAD>(x, lds, c, rb);
-          item_bfly<R2::RB, true, LAZY, false>(x, tw, s0 + R2::SL0, s0, hi, col0 + c, q, nf);
+          item_bfly_t<R2::RB, true, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, c}, s0 + R2::SL0, hi, q, nf);
         }
-        const size_t g = R2::gidx(0, col0 + c, rb);
+        const uint32_t g = R2::gidx(0, col0 + c, rb);
 #pragma unroll
         for (int j = 0; j < R2::E; j += 4) {
           const uint4 k0 = *reinterpret_cast<const uint4*>(k0p + g + j);
@@ -481,6 +518,7 @@ template <int LOGR>
 __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const uint32_t* D, const uint32_t* evk,
                                                        uint32_t* acc, KipArgs A, DevTables T) {
   __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  __shared__ uint2 ltw[Geo<LOGR>::COLS * ((1 << LOGR) - 1)];
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
   const int job = seq % A.n_jobs;
   const int unit = (seq / A.n_jobs) * 8 + xcd;  // (limb e, tile)
@@ -497,9 +535,9 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
   uint32_t* acc_e = acc + (size_t)job * (size_t)A.acc_job + (size_t)e * N;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    kip_b_body<LOGR, true>(Xe, De, evk_e, acc_e, A, lds, e, col0, q, minv, tw);
+    kip_b_body<LOGR, true>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, tw);
   else
-    kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, e, col0, q, minv, tw);
+    kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, tw);
 }
 
 }  // namespace
