@@ -117,6 +117,24 @@ def roofline(prof, steps, N, k, level, K, alpha, jobs):
             "algorithmic_bytes_per_launch": b}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the transform source has changed since the counters
+    were taken (the summary records a hash of it)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_counters_n16_k8_b8.txt")
+    src = os.path.join(ROOT, "paper_2601_15401_amd", "csrc", "ntt.hip")
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        if line.startswith("TRAFFIC "):
+            f = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if f.get("kernel") == kernel and f.get("ntt_sha256_16") == sha:
+                return int(f["bytes"])
+    return None
+
+
 def mult_bytes(N, k, level, K, alpha, jobs):
     """Algorithmic HBM bytes of one multiply in a batch of `jobs` sharing keys:
     k inputs read, the evaluation keys read once per batch, output written."""
@@ -217,6 +235,8 @@ def main():
     value = jobs * args.steps / gpu_s
     log("batched: %.3f ms/step, %.1f ct-mults/s (host wall %.3f s)" % (step_ms.mean(), value, wall))
     rl = roofline(prof, args.steps, N, k, level, K, prm.alpha, jobs)
+    if args.workload == "n16_k8_b8":
+        rl["traffic"] = measured_traffic(rl["kernel"])
 
     plain = None
     if not args.no_plain:
