@@ -38,7 +38,10 @@ WORKLOADS = {
     "n16_k8_b8": (16, 32, 8, 4, 8, 32, 8),
     "n15_k4_b16": (15, 16, 4, 4, 4, 16, 16),
     "n13_k3": (13, 3, 1, 3, 3, 3, 1),
+    "mixed512": None,  # heterogeneous batch, see run_mixed
 }
+# parameter sets of the mixed workload: log_n -> (L, K, dnum)
+MIXED_PARAMS = {13: (3, 1, 3), 14: (8, 2, 4), 15: (16, 4, 4), 16: (32, 8, 4)}
 
 
 def log(*a):
@@ -165,6 +168,134 @@ def cpu_baseline(log_n, L, K, dnum, k, level):
                       "host %s" % (k, log_n, level, k - 1, dt, platform.processor() or platform.machine())}
 
 
+def mixed_jobs(n_jobs, seed):
+    """(log_n, k, level) per job: N uniform over the four sets, k uniform in
+    [2, min(12, L)], level uniform in [k, L]."""
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for _ in range(n_jobs):
+        ln = int(rng.choice(sorted(MIXED_PARAMS)))
+        L = MIXED_PARAMS[ln][0]
+        k = int(rng.integers(2, min(12, L) + 1))
+        level = int(rng.integers(k, L + 1))
+        jobs.append((ln, k, level))
+    return jobs
+
+
+def job_bytes(N, k, level, K, alpha):
+    """Algorithmic HBM bytes of one multiply with its own key reads."""
+    return mult_bytes(N, k, level, K, alpha, 1)
+
+
+def run_mixed(args, torch, mick):
+    """512 multiplies of mixed ring degree, k and level: the batched form runs
+    one plan per ring degree (one launch per stage over a device job table),
+    captured into one graph; the plain form launches each multiply alone."""
+    n_jobs = 512
+    spec = mixed_jobs(n_jobs, 4)
+    prms, keys, pools, specs, plans = {}, {}, {}, {}, {}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    for ln, (L, K, dnum) in MIXED_PARAMS.items():
+        log("params N=2^%d L=%d K=%d dnum=%d; keygen k_max=%d ..." % (ln, L, K, dnum, min(12, L)))
+        prms[ln] = mick.Params(ln, L, K, dnum)
+        keys[ln] = mick.Keys(prms[ln], 40 + ln, min(12, L))
+    log("inputs (uniform residues per limb) ...")
+    for ln, k, level in spec:
+        if (ln, level) not in pools:
+            q = torch.tensor(prms[ln].q[:level], dtype=torch.int64, device="cuda").view(1, 1, level, 1)
+            r = torch.randint(0, 1 << 62, (12, 2, level, 1 << ln), generator=gen, device="cuda", dtype=torch.int64)
+            pools[(ln, level)] = (r % q).to(torch.int32)
+        specs.setdefault(ln, []).append(([pools[(ln, level)][u] for u in range(k)], level, None))
+    for ln in MIXED_PARAMS:
+        if ln in specs:
+            plans[ln] = mick.Plan(prms[ln], keys[ln], specs[ln])
+    torch.cuda.synchronize()
+
+    def step():
+        for p in plans.values():
+            p.run()
+
+    log("warmup ...")
+    mick.profile_enable(True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mick.profile_collect()
+    mick.profile_enable(False)
+    log("capturing one graph of %d plans ..." % len(plans))
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(g, stream=cs):
+            step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record(stream)
+    for i in range(args.steps):
+        g.replay()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    value = n_jobs / (step_ms.mean() / 1e3)
+    log("batched (graph): %.3f ms per 512 multiplies, %.1f ct-mults/s" % (step_ms.mean(), value))
+    # eager steps with the event profiler for the per-site breakdown
+    mick.profile_enable(True)
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    prof = mick.profile_collect()
+    mick.profile_enable(False)
+    for site, (ms, cnt) in sorted(prof.items(), key=lambda x: -x[1][0]):
+        log("  %-20s %8.3f ms/step %5d launches" % (site, ms / 2, cnt // 2))
+
+    plain = None
+    if not args.no_plain:
+        wss = {ln: mick.workspace(prms[ln], mick.OP_MUL_RELIN_RESCALE, min(12, MIXED_PARAMS[ln][0]),
+                                  MIXED_PARAMS[ln][0]) for ln in prms}
+        outs = {ln: [torch.empty(2, lv - len(c) + 1, 1 << ln, dtype=torch.int32, device="cuda")
+                     for c, lv, _ in specs[ln]] for ln in specs}
+
+        def plain_step():
+            for ln in specs:
+                for (c, lv, _), o in zip(specs[ln], outs[ln]):
+                    mick.mul_relin_rescale(prms[ln], keys[ln], c, lv, out=o, ws=wss[ln])
+
+        plain_step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.plain_steps):
+            plain_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / args.plain_steps
+        plain = {"value": round(n_jobs / (pms / 1e3), 2), "unit": "ct-mults/s", "ms_per_512": round(pms, 3)}
+        log("plain: %.3f ms per 512 multiplies, %.1f ct-mults/s" % (pms, n_jobs / (pms / 1e3)))
+        for ln in specs:  # the two forms agree
+            for o, b in zip(outs[ln], plans[ln].outs):
+                assert torch.equal(o, b)
+    total_bytes = sum(job_bytes(1 << ln, k, lv, MIXED_PARAMS[ln][1], prms[ln].alpha) for ln, k, lv in spec)
+    rec = {
+        "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
+        "value": round(value, 2), "unit": "ct-mults/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(float(step_ms.mean()), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "512 multiplies, N uniform over 2^13..2^16, k uniform 2..min(12,L), level "
+                               "uniform k..L, one graph of four job-table plans", "batch": n_jobs,
+                   "parallelism": "none"},
+        "plain": plain,
+        "batched_over_plain": round(value / plain["value"], 3) if plain else None,
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
+                       "p99": round(float(np.percentile(step_ms, 99)), 4), "of": "one batch of 512"},
+        "hbm_frac_whole_path": round(total_bytes / (step_ms.mean() / 1e3) / 1e9 / HBM_PEAK_GBS, 5),
+        "algorithmic_bytes_per_mult": int(total_bytes / n_jobs),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +304,7 @@ def main():
     ap.add_argument("--workload", default="n16_k8_b8", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized buffer once before timing (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -183,8 +315,11 @@ def main():
     import torch
     from paper_2601_15401_amd import mick
 
-    log_n, L, K, dnum, k, level, jobs = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.workload == "mixed512":
+        run_mixed(args, torch, mick)
+        return
+    log_n, L, K, dnum, k, level, jobs = WORKLOADS[args.workload]
     log("params N=2^%d L=%d K=%d dnum=%d; keygen k_max=%d ..." % (log_n, L, K, dnum, k))
     prm = mick.Params(log_n, L, K, dnum)
     keys = mick.Keys(prm, 3, k)

@@ -72,6 +72,7 @@ enum {
 
 typedef struct mick_params mick_params;
 typedef struct mick_keys mick_keys;
+typedef struct mick_plan mick_plan;
 
 const char* mick_strerror(int status);
 const char* mick_last_error(void);
@@ -191,6 +192,39 @@ int mick_mul_relin_rescale(const mick_params* prm, const mick_keys* keys, const 
 size_t mick_batch_workspace_bytes(const mick_params* prm, int n_jobs, int k, int level);
 int mick_mul_relin_rescale_batch(const mick_params* prm, const mick_keys* keys, const uint32_t* cts_dev, int n_jobs,
                                  int k, int level, uint32_t* outs_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* One k-input multiply of a heterogeneous batch. */
+typedef struct mick_job {
+  int k;                     /* 2..12, at most the key set's k_max */
+  int level;                 /* k..L */
+  const uint32_t* cts[12];   /* k device pointers, uint32[2][level][N] each */
+  uint32_t* out;             /* device uint32[2][level-k+1][N] */
+} mick_job;
+
+/* Workspace for mick_mul_relin_rescale_jobs: a job table plus one multiply
+ * workspace per job.  0 for invalid jobs. */
+size_t mick_jobs_workspace_bytes(const mick_params* prm, const mick_job* jobs, int n_jobs);
+
+/* n_jobs (1..65536) multiplies of one parameter set whose k and level may
+ * differ, each bit-identical to mick_mul_relin_rescale.  Every stage of the
+ * multiply is a single launch over a device job table (the tensor product
+ * and the rescale are launched once per distinct k); each workgroup looks
+ * its job up in the table.  jobs: host array; the table is copied into the
+ * workspace (the copy reads `jobs` before the call returns). */
+int mick_mul_relin_rescale_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* The same in two steps.  mick_jobs_plan validates the jobs, writes the job
+ * table (the device work queue) into the workspace with an asynchronous
+ * copy on `stream` and returns a host-side plan; mick_plan_execute enqueues
+ * only kernel launches that read the table, so it can be captured into a HIP
+ * graph and replayed.  The plan refers to the workspace and to the jobs'
+ * buffers, which must stay allocated while it is used; mick_plan_destroy
+ * (NULL-safe) frees only the host object. */
+int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs, void* ws,
+                   size_t ws_bytes, void* stream, mick_plan** out);
+int mick_plan_execute(const mick_plan* plan, void* stream);
+void mick_plan_destroy(mick_plan* plan);
 
 /* Forward / inverse negacyclic NTT of n_limbs limbs in place, limb i taken
  * mod prime index first_prime + i (prime index j < L is q_j, L + i is p_i).

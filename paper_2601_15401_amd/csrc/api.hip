@@ -297,6 +297,16 @@ int build_tables(mick_params* prm) {
   MICK_TRY(dev_alloc(&prm->d_rescale, rs.size()));
   if (!rs.empty()) MICK_HIP(hipMemcpy(prm->d_rescale, rs.data(), rs.size() * 4, hipMemcpyHostToDevice), "rs upload");
 
+  // device copies of the table offsets, for the job-table kernels
+  {
+    std::vector<uint32_t> off;
+    for (size_t v : prm->modup_off) off.push_back((uint32_t)v);
+    for (size_t v : prm->rescale_off) off.push_back((uint32_t)v);
+    for (size_t v : prm->dscale_off) off.push_back((uint32_t)v);
+    MICK_TRY(dev_alloc(&prm->d_offsets, off.size()));
+    MICK_HIP(hipMemcpy(prm->d_offsets, off.data(), off.size() * 4, hipMemcpyHostToDevice), "offset upload");
+  }
+
   // host constants
   prm->pinv_q.resize(L);
   prm->p_mod_q.resize(L);
@@ -468,6 +478,7 @@ void mick_params_destroy(mick_params* prm) {
   if (prm->d_moddown) (void)hipFree(prm->d_moddown);
   if (prm->d_rescale) (void)hipFree(prm->d_rescale);
   if (prm->d_dscale) (void)hipFree(prm->d_dscale);
+  if (prm->d_offsets) (void)hipFree(prm->d_offsets);
   delete prm;
 }
 
@@ -841,6 +852,159 @@ int mick_profile_collect(int max, const char** names, double* total_ms, int* lau
     n++;
   }
   return n;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Blocks of one job in each stage's launch (see the job-table kernels).
+void job_blocks(const mick_params* prm, int k, int level, int (&nb)[kStages]) {
+  const int tiles = 1 << (prm->log_n - 13);
+  const int E = level + prm->K, B = digits_at(prm, level);
+  auto pad8 = [](int x) { return (x + 7) / 8 * 8; };
+  nb[S_TENSOR] = pad8((prm->N / 1024) * level);
+  nb[S_INTT_D] = pad8(tiles * (k - 1) * level);
+  nb[S_MODUP] = pad8((k - 1) * B * tiles) * E;
+  nb[S_KIP] = pad8(E * tiles);
+  nb[S_INTT_ACC] = pad8(tiles * 2 * E);
+  nb[S_MODDOWN] = pad8(2 * (prm->N / 256));
+  nb[S_NTT_OUT] = pad8(tiles * 2 * (level - k + 1));
+}
+
+GroupConsts group_consts(const mick_params* prm, const mick_keys* keys) {
+  GroupConsts G{};
+  G.modup_tab = prm->d_modup;
+  G.modup_off = prm->d_offsets;
+  G.rs_tab = prm->d_rescale;
+  G.rs_off = prm->d_offsets + prm->modup_off.size();
+  G.dscale = prm->d_dscale;
+  G.dscale_off = G.rs_off + prm->rescale_off.size();
+  G.md = prm->d_moddown;
+  G.evk = keys->d_evk;
+  G.log_n = prm->log_n;
+  G.L = prm->L;
+  G.K = prm->K;
+  G.dnum = prm->dnum;
+  G.alpha = prm->alpha;
+  return G;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mick_jobs_workspace_bytes(const mick_params* prm, const mick_job* jobs, int n_jobs) {
+  if (!prm || !jobs || n_jobs < 1) return 0;
+  size_t total = align_up((size_t)n_jobs * sizeof(JobDesc));
+  for (int i = 0; i < n_jobs; i++) {
+    const int k = jobs[i].k, level = jobs[i].level;
+    if (k < 2 || k > kMaxK || level < k || level > prm->L) return 0;
+    total += align_up(WsLayout(k, level, prm->K, prm->alpha, prm->log_n).total * 4);
+  }
+  return total;
+}
+
+int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs, void* ws,
+                   size_t ws_bytes, void* stream, mick_plan** out) {
+  if (!out) return set_error(MICK_E_ARG, "NULL out");
+  *out = nullptr;
+  if (!prm || !keys || !jobs || !ws) return set_error(MICK_E_ARG, "NULL argument");
+  if (keys->prm != prm) return set_error(MICK_E_ARG, "keys belong to other params");
+  if (n_jobs < 1 || n_jobs > 65536) return set_error(MICK_E_ARG, "n_jobs must be in 1..65536");
+  for (int i = 0; i < n_jobs; i++) {
+    const mick_job& jb = jobs[i];
+    MICK_TRY(check_mul(prm, keys, jb.k, jb.level));
+    if (!jb.out) return set_error(MICK_E_ARG, "NULL output pointer");
+    for (int u = 0; u < jb.k; u++)
+      if (!jb.cts[u]) return set_error(MICK_E_ARG, "NULL ciphertext pointer");
+  }
+  if (ws_bytes < mick_jobs_workspace_bytes(prm, jobs, n_jobs)) return set_error(MICK_E_WS, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<mick_plan> plan(new mick_plan());
+  plan->prm = prm;
+  plan->keys = keys;
+  plan->table = (JobDesc*)ws;
+  plan->n_jobs = n_jobs;
+  // jobs of equal k are contiguous in the table (the tensor and rescale kernels
+  // are specialised on k)
+  std::vector<int> order(n_jobs);
+  for (int i = 0; i < n_jobs; i++) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobs[a].k < jobs[b].k; });
+  std::vector<JobDesc> jt(n_jobs);
+  char* base = (char*)ws;
+  size_t off = align_up((size_t)n_jobs * sizeof(JobDesc));
+  int total[kStages] = {0};
+  for (int r = 0; r < n_jobs; r++) {
+    const mick_job& jb = jobs[order[r]];
+    JobDesc& d = jt[r];
+    memset(&d, 0, sizeof(d));
+    for (int u = 0; u < jb.k; u++) d.in[u] = jb.cts[u];
+    d.out = jb.out;
+    d.ws = (uint32_t*)(base + off);
+    d.k = jb.k;
+    d.level = jb.level;
+    off += align_up(WsLayout(jb.k, jb.level, prm->K, prm->alpha, prm->log_n).total * 4);
+    int nb[kStages];
+    job_blocks(prm, jb.k, jb.level, nb);
+    for (int st = 0; st < kStages; st++) {
+      // tensor and rescale launches restart at each run of equal k
+      const bool per_k = st == S_TENSOR || st == S_MODDOWN;
+      if (per_k && r > 0 && jt[r - 1].k != jb.k) {
+        if (st == S_TENSOR) plan->runs.push_back({r, 0, 0, 0});
+        total[st] = 0;
+      }
+      if (per_k && r == 0 && st == S_TENSOR) plan->runs.push_back({0, 0, 0, 0});
+      d.blk0[st] = total[st];
+      total[st] += nb[st];
+    }
+    auto& run = plan->runs.back();
+    run.k = jb.k;
+    run.tensor_blocks = total[S_TENSOR];
+    run.moddown_blocks = total[S_MODDOWN];
+  }
+  for (int st = 0; st < kStages; st++) plan->blocks[st] = total[st];
+  MICK_HIP(hipMemcpyAsync(plan->table, jt.data(), n_jobs * sizeof(JobDesc), hipMemcpyHostToDevice, s), "job table");
+  *out = plan.release();
+  return MICK_OK;
+}
+
+int mick_plan_execute(const mick_plan* plan, void* stream) {
+  if (!plan) return set_error(MICK_E_ARG, "NULL plan");
+  hipStream_t s = (hipStream_t)stream;
+  const mick_params* prm = plan->prm;
+  const JobDesc* djt = plan->table;
+  const int n = plan->n_jobs;
+  const GroupConsts G = group_consts(prm, plan->keys);
+  for (size_t i = 0; i < plan->runs.size(); i++) {
+    const auto& r = plan->runs[i];
+    const int j1 = i + 1 < plan->runs.size() ? plan->runs[i + 1].j0 : n;
+    MICK_TRY(launch_tensor_jt(prm, djt, r.j0, j1 - r.j0, r.k, r.tensor_blocks, s));
+  }
+  MICK_TRY(launch_ntt_jt(prm, djt, n, S_INTT_D, plan->blocks[S_INTT_D], G, s));
+  MICK_TRY(launch_modup_a_jt(prm, djt, n, plan->blocks[S_MODUP], G, s));
+  MICK_TRY(launch_kip_b_jt(prm, djt, n, plan->blocks[S_KIP], G, s));
+  MICK_TRY(launch_ntt_jt(prm, djt, n, S_INTT_ACC, plan->blocks[S_INTT_ACC], G, s));
+  for (size_t i = 0; i < plan->runs.size(); i++) {
+    const auto& r = plan->runs[i];
+    const int j1 = i + 1 < plan->runs.size() ? plan->runs[i + 1].j0 : n;
+    MICK_TRY(launch_moddown_rs_jt(prm, djt, r.j0, j1 - r.j0, r.k - 1, r.moddown_blocks, G, s));
+  }
+  return launch_ntt_jt(prm, djt, n, S_NTT_OUT, plan->blocks[S_NTT_OUT], G, s);
+}
+
+void mick_plan_destroy(mick_plan* plan) { delete plan; }
+
+int mick_mul_relin_rescale_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs,
+                                void* ws, size_t ws_bytes, void* stream) {
+  mick_plan* plan = nullptr;
+  MICK_TRY(mick_jobs_plan(prm, keys, jobs, n_jobs, ws, ws_bytes, stream, &plan));
+  const int st = mick_plan_execute(plan, stream);
+  mick_plan_destroy(plan);
+  return st;
 }
 
 int mick_ntt(const mick_params* prm, uint32_t* data_dev, int n_limbs, int first_prime, int inverse, void* stream) {

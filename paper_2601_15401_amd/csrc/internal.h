@@ -40,6 +40,63 @@ struct LimbMap {
   const uint32_t* nfix_pos;
 };
 
+// Workspace of one k-input multiply at `level`, in elements: the tensor
+// product D [k+1][level][N], the scaled coefficient-domain d_2..d_k
+// [k-1][level][N], the ModUp pass-A outputs [k-1][B][level+K][N] and the two
+// accumulators [2][level+K][N].
+struct WsLayout {
+  size_t D, dcoef, X, acc, total;
+  __host__ __device__ WsLayout(int k, int level, int K, int alpha, int log_n) {
+    const size_t N = (size_t)1 << log_n;
+    const int E = level + K, B = (level + alpha - 1) / alpha;
+    D = 0;
+    dcoef = D + (size_t)(k + 1) * level * N;
+    X = dcoef + (size_t)(k - 1) * level * N;
+    acc = X + (size_t)(k - 1) * B * E * N;
+    total = acc + 2 * (size_t)E * N;
+  }
+};
+
+// Heterogeneous batches: every stage of the multiply is one launch over a
+// table of jobs of one ring degree (the jobs' k and level may differ); each
+// block finds its job by binary search over the jobs' first blocks.
+enum Stage { S_TENSOR, S_INTT_D, S_MODUP, S_KIP, S_INTT_ACC, S_MODDOWN, S_NTT_OUT, kStages };
+
+struct JobDesc {
+  const uint32_t* in[kMaxK];  // input ciphertexts [2][level][N]
+  uint32_t* out;              // output [2][level-k+1][N]
+  uint32_t* ws;               // the job's workspace (WsLayout)
+  int k, level;
+  int blk0[kStages];          // first block of the job in each stage's launch (multiple of 8)
+};
+
+// Index (relative to jt) of the last job whose first block in `stage` is <= b.
+__device__ __forceinline__ int find_job(const JobDesc* jt, int n, int stage, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jt[mid].blk0[stage] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Per parameter set and key set: what the table kernels read besides the
+// job table.  Offsets are element offsets into the parameter tables.
+struct GroupConsts {
+  const uint32_t* modup_tab;
+  const uint32_t* modup_off;   // [L][dnum]: offset of the (level, digit) table
+  const uint32_t* rs_tab;
+  const uint32_t* rs_off;      // [L+1][L+1]: offset of the (level, mu) table
+  const uint32_t* dscale;
+  const uint32_t* dscale_off;  // [L+1]
+  const uint32_t* md;          // ModDown constants
+  const uint32_t* evk;
+  int log_n, L, K, dnum, alpha;
+};
+
 struct mick_params_impl;
 
 }  // namespace mick
@@ -62,12 +119,28 @@ struct mick_params {
   // qhat_j^-1 (within its digit) folded in, [level][4]
   uint32_t* d_dscale = nullptr;
   std::vector<size_t> dscale_off;  // index level
+  // device copies of modup_off, rescale_off and dscale_off (uint32)
+  uint32_t* d_offsets = nullptr;
   std::vector<size_t> rescale_off;  // index level * (L + 1) + mu
   // P^-1 and P mod q_j (host)
   std::vector<uint32_t> pinv_q, p_mod_q;
   // host copies of psi per prime
   std::vector<uint32_t> psi;
   int split_a, split_b;  // log2 rows of the two NTT passes
+};
+
+// A heterogeneous batch ready to run: the job table lives in the caller's
+// workspace, the launch sizes here.
+struct mick_plan {
+  const mick_params* prm;
+  const mick_keys* keys;
+  mick::JobDesc* table;
+  int n_jobs;
+  int blocks[mick::kStages];
+  struct Run {  // jobs [j0, next j0) share k
+    int j0, k, tensor_blocks, moddown_blocks;
+  };
+  std::vector<Run> runs;
 };
 
 struct mick_keys {

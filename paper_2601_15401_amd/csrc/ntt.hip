@@ -540,6 +540,160 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
     kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, tw);
 }
 
+// ------------------------------------------------------------------ job-table forms
+
+// One transform pass over the jobs of a table: stage S_INTT_D (d_2..d_k into
+// the scaled coefficient limbs), S_INTT_ACC (the accumulators) or S_NTT_OUT
+// (the rescaled output).  Blocks per job: tiles x limbs.
+template <int LOGR, bool FWD, bool PASSB>
+__global__ __launch_bounds__(kThreads) void k_ntt_pass_jt(const JobDesc* jt, int nj, int stage, GroupConsts G,
+                                                          DevTables T, int s0) {
+  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  constexpr bool FIRST = FWD ? !PASSB : PASSB;  // the transform's first pass reads the source
+  const int j = find_job(jt, nj, stage, blockIdx.x);
+  const int local = blockIdx.x - jt[j].blk0[stage];
+  const int log_n = G.log_n;
+  const int tiles = 1 << (log_n - kTileLog);
+  const int tile = local & (tiles - 1), limb = local >> (log_n - kTileLog);
+  const int k = jt[j].k, level = jt[j].level;
+  const size_t N = (size_t)1 << log_n;
+  const WsLayout lay(k, level, G.K, G.alpha, log_n);
+  uint32_t* ws = jt[j].ws;
+  const uint32_t* src;
+  uint32_t* dst;
+  int prime;
+  uint4 nfix;
+  if (stage == S_INTT_D) {
+    if (limb >= (k - 1) * level) return;
+    const int g = limb / level, pos = limb - g * level;
+    prime = pos;
+    dst = ws + lay.dcoef + ((size_t)g * level + pos) * N;
+    src = FIRST ? ws + lay.D + ((size_t)(g + 2) * level + pos) * N : dst;
+    nfix = reinterpret_cast<const uint4*>(G.dscale + G.dscale_off[level])[pos];
+  } else if (stage == S_INTT_ACC) {
+    const int E = level + G.K;
+    if (limb >= 2 * E) return;
+    const int g = limb / E, pos = limb - g * E;
+    prime = pos < level ? pos : G.L + (pos - level);
+    dst = ws + lay.acc + ((size_t)g * E + pos) * N;
+    src = dst;
+    nfix = reinterpret_cast<const uint4*>(T.nfix)[prime];
+  } else {
+    const int top = level - (k - 1);
+    if (limb >= 2 * top) return;
+    const int g = limb / top, pos = limb - g * top;
+    prime = pos;
+    dst = jt[j].out + ((size_t)g * top + pos) * N;
+    src = dst;
+    nfix = reinterpret_cast<const uint4*>(T.nfix)[prime];
+  }
+  const uint32_t q = T.mod[prime];
+  const uint2* tw = reinterpret_cast<const uint2*>(FWD ? T.tw : T.itw) + ((size_t)prime << log_n);
+  const int H = log_n - s0 - LOGR;
+  const int col0 = tile * Geo<LOGR>::COLS;
+  if (q < (1u << 30))
+    pass_body<LOGR, FWD, true, PASSB>(src, dst, lds, s0, H, col0, q, tw, nfix);
+  else
+    pass_body<LOGR, FWD, false, PASSB>(src, dst, lds, s0, H, col0, q, tw, nfix);
+}
+
+// ModUp conversion + pass A over the jobs of a table.  Blocks per job:
+// ceil(units / 8) 8 E with units = (k - 1) B tiles (each job's first block is
+// a multiple of 8, so local and global blocks share their XCD).
+template <int LOGR, int ALPHA>
+__global__ __launch_bounds__(kThreads) void k_modup_a_jt(const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
+  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  const int j = find_job(jt, nj, S_MODUP, blockIdx.x);
+  const int local = blockIdx.x - jt[j].blk0[S_MODUP];
+  const int log_n = G.log_n;
+  const int k = jt[j].k, level = jt[j].level;
+  const int E = level + G.K, B = (level + G.alpha - 1) / G.alpha;
+  const int tiles = 1 << (log_n - kTileLog);
+  const int units = (k - 1) * B * tiles;
+  const int xcd = local & 7, seq = local >> 3;
+  const int e = seq % E;
+  const int unit = (seq / E) * 8 + xcd;
+  if (unit >= units) return;
+  const int tile = unit % tiles;
+  const int tb = unit / tiles;  // (t - 2) B + b
+  const int t2 = tb / B, b = tb - t2 * B;
+  const int lo = b * G.alpha;
+  const int na = min(G.alpha, level - lo);
+  if (e >= lo && e < lo + na) return;
+  const int pe = e < level ? e : G.L + (e - level);
+  const uint32_t q = T.mod[pe], minv = T.minv[pe];
+  const uint2* tw = reinterpret_cast<const uint2*>(T.tw) + ((size_t)pe << log_n);
+  const size_t N = (size_t)1 << log_n;
+  const WsLayout lay(k, level, G.K, G.alpha, log_n);
+  const uint32_t* C = G.modup_tab + G.modup_off[(level - 1) * G.dnum + b] + 2 * ALPHA;
+  const uint32_t* base = jt[j].ws + lay.dcoef + ((size_t)t2 * level + lo) * N;
+  const uint32_t* srow[ALPHA];
+  uint32_t cc[ALPHA];
+#pragma unroll
+  for (int a = 0; a < ALPHA; a++) {
+    srow[a] = base + (size_t)min(a, na - 1) * N;
+    cc[a] = C[a * E + e];
+  }
+  uint32_t* dst = jt[j].ws + lay.X + ((size_t)tb * E + e) * N;
+  const int H = log_n - LOGR;
+  const int col0 = tile * Geo<LOGR>::COLS;
+  if (q < (1u << 30))
+    modup_a_body<LOGR, ALPHA, true>(srow, cc, minv, dst, lds, H, col0, q, tw);
+  else
+    modup_a_body<LOGR, ALPHA, false>(srow, cc, minv, dst, lds, H, col0, q, tw);
+}
+
+// Pass B + key inner product over the jobs of a table.  Blocks per job:
+// ceil(E tiles / 8) 8.
+template <int LOGR>
+__global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
+  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  __shared__ uint2 ltw[Geo<LOGR>::COLS * ((1 << LOGR) - 1)];
+  const int j = find_job(jt, nj, S_KIP, blockIdx.x);
+  const int local = blockIdx.x - jt[j].blk0[S_KIP];
+  const int log_n = G.log_n;
+  const int k = jt[j].k, level = jt[j].level;
+  KipArgs A{};
+  A.log_n = log_n;
+  A.level = level;
+  A.L = G.L;
+  A.E = level + G.K;
+  A.B = (level + G.alpha - 1) / G.alpha;
+  A.alpha = G.alpha;
+  A.dnum = G.dnum;
+  A.k = k;
+  A.n_jobs = 1;
+  A.tiles = 1 << (log_n - kTileLog);
+  A.key_poly = (long long)(G.L + G.K) << log_n;
+  const int unit = (local >> 3) * 8 + (local & 7);
+  if (unit >= A.E * A.tiles) return;
+  const int e = unit / A.tiles;
+  const int tile = unit - e * A.tiles;
+  const int pe = e < level ? e : G.L + (e - level);
+  const uint32_t q = T.mod[pe], minv = T.minv[pe];
+  const uint2* tw = reinterpret_cast<const uint2*>(T.tw) + ((size_t)pe << log_n);
+  const size_t N = (size_t)1 << log_n;
+  const WsLayout lay(k, level, G.K, G.alpha, log_n);
+  uint32_t* ws = jt[j].ws;
+  const int col0 = tile * Geo<LOGR>::COLS;
+  if (q < (1u << 30))
+    kip_b_body<LOGR, true>(ws + lay.X + (size_t)e * N, ws + lay.D + (size_t)e * N, G.evk + (size_t)pe * N,
+                           ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, tw);
+  else
+    kip_b_body<LOGR, false>(ws + lay.X + (size_t)e * N, ws + lay.D + (size_t)e * N, G.evk + (size_t)pe * N,
+                            ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, tw);
+}
+
+template <bool FWD, bool PASSB>
+void launch_pass_jt(int logr, unsigned blocks, hipStream_t s, const JobDesc* jt, int nj, int stage,
+                    const GroupConsts& G, const DevTables& T, int s0) {
+  switch (logr) {
+    case 6: k_ntt_pass_jt<6, FWD, PASSB><<<blocks, kThreads, 0, s>>>(jt, nj, stage, G, T, s0); break;
+    case 7: k_ntt_pass_jt<7, FWD, PASSB><<<blocks, kThreads, 0, s>>>(jt, nj, stage, G, T, s0); break;
+    default: k_ntt_pass_jt<8, FWD, PASSB><<<blocks, kThreads, 0, s>>>(jt, nj, stage, G, T, s0); break;
+  }
+}
+
 }  // namespace
 
 LimbMap simple_map(const mick_params* prm, int first_prime, int n_limbs) {
@@ -607,6 +761,69 @@ int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, c
     case 6: k_kip_b<6><<<blocks, kKipThreads, 0, s>>>(X, D, evk, acc, A, T); break;
     case 7: k_kip_b<7><<<blocks, kKipThreads, 0, s>>>(X, D, evk, acc, A, T); break;
     default: k_kip_b<8><<<blocks, kKipThreads, 0, s>>>(X, D, evk, acc, A, T); break;
+  }
+  return hip_error(hipGetLastError(), "kip launch");
+}
+
+}  // namespace mick
+
+namespace mick {
+
+int launch_ntt_jt(const mick_params* prm, const JobDesc* jt, int nj, int stage, int blocks, const GroupConsts& G,
+                  hipStream_t s) {
+  if (blocks <= 0) return MICK_OK;
+  const int la = prm->split_a, lb = prm->split_b;
+  const int site = stage == S_INTT_D ? P_INTT_D : (stage == S_INTT_ACC ? P_INTT_ACC : P_NTT_OUT);
+  if (stage == S_NTT_OUT) {
+    {
+      ProfScope ps(site, s);
+      launch_pass_jt<true, false>(la, blocks, s, jt, nj, stage, G, prm->dt, 0);
+    }
+    ProfScope ps(site + 1, s);
+    launch_pass_jt<true, true>(lb, blocks, s, jt, nj, stage, G, prm->dt, la);
+  } else {
+    {
+      ProfScope ps(site + 1, s);
+      launch_pass_jt<false, true>(lb, blocks, s, jt, nj, stage, G, prm->dt, la);
+    }
+    ProfScope ps(site, s);
+    launch_pass_jt<false, false>(la, blocks, s, jt, nj, stage, G, prm->dt, 0);
+  }
+  return hip_error(hipGetLastError(), "ntt launch");
+}
+
+int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blocks, const GroupConsts& G,
+                      hipStream_t s) {
+  if (blocks <= 0) return MICK_OK;
+  ProfScope ps(P_MODUP, s);
+  const DevTables& T = prm->dt;
+#define MICK_MA(LR, AL) k_modup_a_jt<LR, AL><<<blocks, kThreads, 0, s>>>(jt, nj, G, T)
+#define MICK_MA_A(LR)               \
+  switch (modup_rows(G.alpha)) {    \
+    case 1: MICK_MA(LR, 1); break;  \
+    case 2: MICK_MA(LR, 2); break;  \
+    case 4: MICK_MA(LR, 4); break;  \
+    default: MICK_MA(LR, 8); break; \
+  }
+  if (prm->split_a == 7) {
+    MICK_MA_A(7)
+  } else {
+    MICK_MA_A(8)
+  }
+#undef MICK_MA_A
+#undef MICK_MA
+  return hip_error(hipGetLastError(), "modup launch");
+}
+
+int launch_kip_b_jt(const mick_params* prm, const JobDesc* jt, int nj, int blocks, const GroupConsts& G,
+                    hipStream_t s) {
+  if (blocks <= 0) return MICK_OK;
+  ProfScope ps(P_KIP, s);
+  const DevTables& T = prm->dt;
+  switch (prm->split_b) {
+    case 6: k_kip_b_jt<6><<<blocks, kKipThreads, 0, s>>>(jt, nj, G, T); break;
+    case 7: k_kip_b_jt<7><<<blocks, kKipThreads, 0, s>>>(jt, nj, G, T); break;
+    default: k_kip_b_jt<8><<<blocks, kKipThreads, 0, s>>>(jt, nj, G, T); break;
   }
   return hip_error(hipGetLastError(), "kip launch");
 }

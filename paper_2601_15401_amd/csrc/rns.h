@@ -51,6 +51,18 @@ int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, c
                  KipArgs A, hipStream_t s);
 int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out, const MdArgs& A, int mu, int n_jobs,
                       hipStream_t s);
+// Job-table forms (heterogeneous batches): jobs [j0, j0 + nj) of the table,
+// all with the given k (mu = k - 1); `blocks` covers their block ranges.
+int launch_tensor_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks, hipStream_t s);
+int launch_moddown_rs_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int mu, int blocks,
+                         const GroupConsts& G, hipStream_t s);
+int launch_ntt_jt(const mick_params* prm, const JobDesc* jt, int nj, int stage, int blocks, const GroupConsts& G,
+                  hipStream_t s);
+int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blocks, const GroupConsts& G,
+                      hipStream_t s);
+int launch_kip_b_jt(const mick_params* prm, const JobDesc* jt, int nj, int blocks, const GroupConsts& G,
+                    hipStream_t s);
+
 int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout, const MdArgs& A, int mu,
                    hipStream_t s);
 int launch_rs_combine(const mick_params* prm, const uint32_t* Ain, const uint32_t* Bn, uint32_t* out, const MdArgs& A,

@@ -23,25 +23,19 @@ __device__ __forceinline__ uint32_t mul_var(uint32_t a, uint32_t b, uint32_t m, 
 // built one factor at a time; every partial product picks up one R^-1 per
 // factor, removed at the end by R^(k-1).
 template <int K>
-__global__ __launch_bounds__(kThreads) void k_tensor(CtPtrs in, long long in_job_stride, int level, int log_n,
-                                                     uint32_t* D, long long d_job_stride, DevTables T) {
-  const int j = blockIdx.y;
-  const size_t n = (size_t)blockIdx.x * kThreads + threadIdx.x;  // uint4 index
+__device__ __forceinline__ void tensor_body(const uint32_t* const (&inp)[K], int level, int log_n, uint32_t* D, int j,
+                                            size_t n, const DevTables& T) {
   const size_t N = (size_t)1 << log_n;
   const uint32_t m = T.mod[j], minv = T.minv[j];
-  const size_t job_in = (size_t)blockIdx.z * (size_t)in_job_stride;
   const size_t limb = (size_t)j * N;
   const size_t poly = (size_t)level * N;
   uint4 P[K + 1];
-  {
-    const uint4* c = reinterpret_cast<const uint4*>(in.p[0] + job_in + limb);
-    P[0] = c[n];
-    P[1] = reinterpret_cast<const uint4*>(in.p[0] + job_in + poly + limb)[n];
-  }
+  P[0] = reinterpret_cast<const uint4*>(inp[0] + limb)[n];
+  P[1] = reinterpret_cast<const uint4*>(inp[0] + poly + limb)[n];
 #pragma unroll
   for (int u = 1; u < K; u++) {
-    const uint4 a = reinterpret_cast<const uint4*>(in.p[u] + job_in + limb)[n];
-    const uint4 b = reinterpret_cast<const uint4*>(in.p[u] + job_in + poly + limb)[n];
+    const uint4 a = reinterpret_cast<const uint4*>(inp[u] + limb)[n];
+    const uint4 b = reinterpret_cast<const uint4*>(inp[u] + poly + limb)[n];
     // new_t = P_t a + P_{t-1} b, t = u+1 .. 0 (descending keeps P_{t-1} intact)
     P[u + 1].x = mont_mul(P[u].x, b.x, m, minv);
     P[u + 1].y = mont_mul(P[u].y, b.y, m, minv);
@@ -61,7 +55,7 @@ __global__ __launch_bounds__(kThreads) void k_tensor(CtPtrs in, long long in_job
   }
   const uint32_t* rp = T.rpow + (size_t)j * 2 * (kMaxK + 1);
   const uint32_t f = rp[2 * (K - 1)], fsh = rp[2 * (K - 1) + 1];
-  uint32_t* out = D + (size_t)blockIdx.z * (size_t)d_job_stride + limb;
+  uint32_t* out = D + limb;
 #pragma unroll
   for (int t = 0; t <= K; t++) {
     uint4 v;
@@ -73,6 +67,31 @@ __global__ __launch_bounds__(kThreads) void k_tensor(CtPtrs in, long long in_job
   }
 }
 
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_tensor(CtPtrs in, long long in_job_stride, int level, int log_n,
+                                                     uint32_t* D, long long d_job_stride, DevTables T) {
+  const size_t job_in = (size_t)blockIdx.z * (size_t)in_job_stride;
+  const uint32_t* inp[K];
+#pragma unroll
+  for (int u = 0; u < K; u++) inp[u] = in.p[u] + job_in;
+  tensor_body<K>(inp, level, log_n, D + (size_t)blockIdx.z * (size_t)d_job_stride, blockIdx.y,
+                 (size_t)blockIdx.x * kThreads + threadIdx.x, T);
+}
+
+// Job-table form: jobs [j0, j0 + nj) of equal k; blocks per job (N / 1024) level.
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_tensor_jt(const JobDesc* jt, int j0, int nj, int log_n, DevTables T) {
+  const int j = j0 + find_job(jt + j0, nj, S_TENSOR, blockIdx.x);
+  const int local = blockIdx.x - jt[j].blk0[S_TENSOR];
+  const int xb = 1 << (log_n - 10);
+  const int level = jt[j].level;
+  if (local >= xb * level) return;
+  const uint32_t* inp[K];
+#pragma unroll
+  for (int u = 0; u < K; u++) inp[u] = jt[j].in[u];
+  tensor_body<K>(inp, level, log_n, jt[j].ws, local / xb, (size_t)(local % xb) * kThreads + threadIdx.x, T);
+}
+
 // ------------------------------------------------------------------ ModDown + multi-rescale
 // Input: acc after the INTT, coefficient domain: rows q_0..q_{l-1} hold
 // INTT(D + P^-1 C~) (eq. (moddown improved 2)), rows p_i hold INTT(C~^(p)).
@@ -81,13 +100,11 @@ __global__ __launch_bounds__(kThreads) void k_tensor(CtPtrs in, long long in_job
 // every kept limb eta takes g^{mu,l-1}_eta c*_eta - sum_t g^{mu,t}_eta a_t.
 // Output coefficient domain, limbs 0..l-mu-1 (the final NTT follows).
 template <int MU>
-__global__ __launch_bounds__(kThreads) void k_moddown_rs(const uint32_t* acc, uint32_t* out, MdArgs A, DevTables T) {
+__device__ __forceinline__ void moddown_body(const uint32_t* acc, uint32_t* out, const MdArgs& A, int l, size_t n,
+                                             const DevTables& T) {
   const size_t N = (size_t)1 << A.log_n;
-  const size_t n = (size_t)blockIdx.x * kThreads + threadIdx.x;
-  const int l = blockIdx.y;
-  const size_t job = blockIdx.z;
-  const uint32_t* row = acc + job * (size_t)A.acc_job + (size_t)l * A.E * N + n;
-  uint32_t* o = out + job * (size_t)A.out_job + (size_t)l * (A.level - MU) * N + n;
+  const uint32_t* row = acc + (size_t)l * A.E * N + n;
+  uint32_t* o = out + (size_t)l * (A.level - MU) * N + n;
   // scaled p residues z_i = [phat_i^-1 x_i]_{p_i}
   uint32_t z[kMaxKp];
 #pragma unroll
@@ -143,6 +160,35 @@ __global__ __launch_bounds__(kThreads) void k_moddown_rs(const uint32_t* acc, ui
       o[(size_t)eta * N] = sub_mod(a, reduce64(s, rc), rc.m);
     }
   }
+}
+
+template <int MU>
+__global__ __launch_bounds__(kThreads) void k_moddown_rs(const uint32_t* acc, uint32_t* out, MdArgs A, DevTables T) {
+  const size_t job = blockIdx.z;
+  moddown_body<MU>(acc + job * (size_t)A.acc_job, out + job * (size_t)A.out_job, A, blockIdx.y,
+                   (size_t)blockIdx.x * kThreads + threadIdx.x, T);
+}
+
+// Job-table form: jobs [j0, j0 + nj) of equal k = MU + 1; blocks per job 2 N / 256.
+template <int MU>
+__global__ __launch_bounds__(kThreads) void k_moddown_rs_jt(const JobDesc* jt, int j0, int nj, GroupConsts G,
+                                                            DevTables T) {
+  const int j = j0 + find_job(jt + j0, nj, S_MODDOWN, blockIdx.x);
+  const int local = blockIdx.x - jt[j].blk0[S_MODDOWN];
+  const int xb = 1 << (G.log_n - 8);
+  if (local >= 2 * xb) return;
+  const int level = jt[j].level;
+  MdArgs A{};
+  A.md = G.md;
+  A.qinvq = G.md + 2 * G.K + (size_t)G.K * G.L;
+  A.rs = MU > 0 ? G.rs_tab + G.rs_off[level * (G.L + 1) + MU] : nullptr;
+  A.log_n = G.log_n;
+  A.level = level;
+  A.L = G.L;
+  A.K = G.K;
+  A.E = level + G.K;
+  const WsLayout lay(MU + 1, level, G.K, G.alpha, G.log_n);
+  moddown_body<MU>(jt[j].ws + lay.acc, jt[j].out, A, local / xb, (size_t)(local % xb) * kThreads + threadIdx.x, T);
 }
 
 // Algorithm 1 step 2 and the sums of step 3 on coefficient-domain dropped
@@ -281,6 +327,36 @@ int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out
   case MM: k_moddown_rs<MM><<<grid, kThreads, 0, s>>>(acc, out, A, T); break;
     MICK_M(0) MICK_M(1) MICK_M(2) MICK_M(3) MICK_M(4) MICK_M(5) MICK_M(6) MICK_M(7) MICK_M(8) MICK_M(9) MICK_M(10)
     MICK_M(11)
+#undef MICK_M
+    default: return set_error(MICK_E_ARG, "mu out of range for the fused rescale");
+  }
+  return hip_error(hipGetLastError(), "moddown launch");
+}
+
+int launch_tensor_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks, hipStream_t s) {
+  if (blocks <= 0) return MICK_OK;
+  const DevTables& T = prm->dt;
+  const int ln = prm->log_n;
+  ProfScope ps(P_TENSOR, s);
+  switch (k) {
+#define MICK_T(KK) \
+  case KK: k_tensor_jt<KK><<<blocks, kThreads, 0, s>>>(jt, j0, nj, ln, T); break;
+    MICK_T(2) MICK_T(3) MICK_T(4) MICK_T(5) MICK_T(6) MICK_T(7) MICK_T(8) MICK_T(9) MICK_T(10) MICK_T(11) MICK_T(12)
+#undef MICK_T
+    default: return set_error(MICK_E_ARG, "k out of range");
+  }
+  return hip_error(hipGetLastError(), "tensor launch");
+}
+
+int launch_moddown_rs_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int mu, int blocks,
+                         const GroupConsts& G, hipStream_t s) {
+  if (blocks <= 0) return MICK_OK;
+  const DevTables& T = prm->dt;
+  ProfScope ps(P_MODDOWN_RS, s);
+  switch (mu) {
+#define MICK_M(MM) \
+  case MM: k_moddown_rs_jt<MM><<<blocks, kThreads, 0, s>>>(jt, j0, nj, G, T); break;
+    MICK_M(1) MICK_M(2) MICK_M(3) MICK_M(4) MICK_M(5) MICK_M(6) MICK_M(7) MICK_M(8) MICK_M(9) MICK_M(10) MICK_M(11)
 #undef MICK_M
     default: return set_error(MICK_E_ARG, "mu out of range for the fused rescale");
   }

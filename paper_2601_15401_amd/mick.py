@@ -51,12 +51,24 @@ _SIGS = {
     "mick_mul_relin_rescale_batch": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
                                                     _vp, ctypes.c_size_t, _vp]),
     "mick_ntt": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "mick_jobs_workspace_bytes": (ctypes.c_size_t, [_vp, _vp, ctypes.c_int]),
+    "mick_mul_relin_rescale_jobs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t, _vp]),
+    "mick_jobs_plan": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t, _vp,
+                                      ctypes.POINTER(_vp)]),
+    "mick_plan_execute": (ctypes.c_int, [_vp, _vp]),
+    "mick_plan_destroy": (None, [_vp]),
     "mick_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "mick_profile_collect": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
 }
 
 _lib = None
+
+
+class Job(ctypes.Structure):
+    """mick_job: one multiply of a heterogeneous batch."""
+    _fields_ = [("k", ctypes.c_int), ("level", ctypes.c_int), ("cts", ctypes.c_void_p * 12),
+                ("out", ctypes.c_void_p)]
 
 
 class MickError(RuntimeError):
@@ -280,6 +292,64 @@ def mul_relin_rescale_batch(prm: Params, keys: Keys, cts: torch.Tensor, level: i
     _check(load().mick_mul_relin_rescale_batch(prm.handle, keys.handle, _ptr(cts), n_jobs, k, level, _ptr(out),
                                                _ptr(ws), ws.numel() * 4, _stream()), "mick_mul_relin_rescale_batch")
     return out
+
+
+def make_jobs(prm: Params, specs):
+    """specs: list of (cts, level, out) with cts a list of [2, level, N] tensors
+    and out a [2, level - k + 1, N] tensor or None.  Returns (ctypes array,
+    outputs)."""
+    arr = (Job * len(specs))()
+    outs = []
+    for i, (cts, level, out) in enumerate(specs):
+        k = len(cts)
+        if out is None:
+            out = _dev_empty(2, level - k + 1, prm.N)
+        arr[i].k, arr[i].level = k, level
+        for u, c in enumerate(cts):
+            arr[i].cts[u] = _ptr(c).value
+        arr[i].out = _ptr(out).value
+        outs.append(out)
+    return arr, outs
+
+
+def jobs_workspace(prm: Params, arr) -> torch.Tensor:
+    nbytes = load().mick_jobs_workspace_bytes(prm.handle, ctypes.cast(arr, _vp), len(arr))
+    if nbytes == 0:
+        raise ValueError("invalid jobs")
+    return _dev_empty((nbytes + 3) // 4)
+
+
+def mul_relin_rescale_jobs(prm: Params, keys: Keys, specs, ws=None):
+    """Heterogeneous batch: every job (k, level may differ) in one launch per stage."""
+    arr, outs = make_jobs(prm, specs)
+    if ws is None:
+        ws = jobs_workspace(prm, arr)
+    _check(load().mick_mul_relin_rescale_jobs(prm.handle, keys.handle, ctypes.cast(arr, _vp), len(arr), _ptr(ws),
+                                              ws.numel() * 4, _stream()), "mick_mul_relin_rescale_jobs")
+    return outs
+
+
+class Plan:
+    """A heterogeneous batch whose job table has been written to `ws`.  run()
+    only launches kernels, so it can be captured into a CUDA/HIP graph."""
+
+    def __init__(self, prm: Params, keys: Keys, specs, ws=None):
+        self.arr, self.outs = make_jobs(prm, specs)
+        self.ws = jobs_workspace(prm, self.arr) if ws is None else ws
+        self.prm, self.keys, self.specs = prm, keys, specs  # keep the buffers alive
+        h = _vp()
+        _check(load().mick_jobs_plan(prm.handle, keys.handle, ctypes.cast(self.arr, _vp), len(self.arr),
+                                     _ptr(self.ws), self.ws.numel() * 4, _stream(), ctypes.byref(h)), "mick_jobs_plan")
+        self._h = h
+
+    def run(self):
+        _check(load().mick_plan_execute(self._h, _stream()), "mick_plan_execute")
+        return self.outs
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mick_plan_destroy(self._h)
+            self._h = None
 
 
 def ntt(prm: Params, data: torch.Tensor, first_prime: int, inverse: bool = False) -> torch.Tensor:

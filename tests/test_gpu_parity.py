@@ -183,6 +183,57 @@ def test_batch_equals_plain_and_oracle(hyb):
         _eq(out[j], mult.mul_relin_rescale(c.op, c.ok, list(cts[j]), level), "batch job %d" % j)
 
 
+def test_heterogeneous_jobs_equal_plain(hyb):
+    """A mixed batch (different k and level per job, one launch per stage) gives
+    each job the bits of its own plain call, and the oracle's."""
+    c = hyb
+    rng = np.random.default_rng(700)
+    shapes = [(2, 8), (3, 5), (2, 2), (6, 8), (4, 7), (3, 3), (5, 6), (2, 8), (6, 6)]
+    specs, host = [], []
+    for k, level in shapes:
+        cts = [np.stack([_rand_poly(rng, c.op.q[:level], c.op.N) for _ in range(2)]) for _ in range(k)]
+        host.append((cts, level))
+        specs.append(([mick.from_numpy_u32(x) for x in cts], level, None))
+    outs = mick.mul_relin_rescale_jobs(c.prm, c.gk, specs)
+    for (cts_d, level, _), out, (cts, _) in zip(specs, outs, host):
+        assert torch.equal(out, mick.mul_relin_rescale(c.prm, c.gk, cts_d, level))
+    for i in (0, 3, 5):
+        cts, level = host[i]
+        _eq(outs[i], mult.mul_relin_rescale(c.op, c.ok, cts, level), "mixed job %d" % i)
+
+
+def test_plan_replayed_from_a_graph(hyb):
+    """The execute step of a planned batch is captured into a graph; every
+    replay (with eager work in between) matches the eager run."""
+    c = hyb
+    rng = np.random.default_rng(800)
+    shapes = [(3, 8), (2, 4), (5, 7)]
+    specs = []
+    for k, level in shapes:
+        cts = [mick.from_numpy_u32(np.stack([_rand_poly(rng, c.op.q[:level], c.op.N) for _ in range(2)]))
+               for _ in range(k)]
+        specs.append((cts, level, None))
+    plan = mick.Plan(c.prm, c.gk, specs)
+    eager = [o.clone() for o in plan.run()]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.run()
+    for rep in range(3):
+        for o in plan.outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(plan.outs, eager):
+            assert torch.equal(o, e), rep
+        # eager work between replays
+        mick.mul_relin_rescale(c.prm, c.gk, specs[0][0], 8)
+        torch.cuda.synchronize()
+
+
 def test_repeated_calls_are_deterministic(hyb):
     c = hyb
     rng = np.random.default_rng(600)
