@@ -39,6 +39,7 @@ WORKLOADS = {
     "n15_k4_b16": (15, 16, 4, 4, 4, 16, 16),
     "n13_k3": (13, 3, 1, 3, 3, 3, 1),
     "mixed512": None,  # heterogeneous batch, see run_mixed
+    "serve5000": None,  # open-loop serving, see run_serve
 }
 # parameter sets of the mixed workload: log_n -> (L, K, dnum)
 MIXED_PARAMS = {13: (3, 1, 3), 14: (8, 2, 4), 15: (16, 4, 4), 16: (32, 8, 4)}
@@ -296,6 +297,117 @@ def run_mixed(args, torch, mick):
     print(json.dumps(rec), flush=True)
 
 
+def run_serve(args, torch, mick):
+    """Open-loop serving of 5000 requests (the mixed-workload mixture plus 10%
+    heavy N = 2^16, k = 12 requests) through the continuous-batching server:
+    first all requests at once (saturation throughput), then Poisson
+    arrivals at 0.5 / 0.8 / 0.95 of that rate.  Latency is completion (a HIP
+    event after the request's plan) minus scheduled arrival."""
+    from paper_2601_15401_amd import serve
+    n_req = 5000
+    budget = 200 * 10 ** 9
+    mix = serve.request_mix(n_req, 5, MIXED_PARAMS)
+    free0, total = torch.cuda.mem_get_info()
+    prms, keys, pools = {}, {}, {}
+    for ln, (L, K, dnum) in MIXED_PARAMS.items():
+        log("params N=2^%d L=%d K=%d dnum=%d; keygen k_max=%d ..." % (ln, L, K, dnum, min(12, L)))
+        prms[ln] = mick.Params(ln, L, K, dnum)
+        keys[ln] = mick.Keys(prms[ln], 50 + ln, min(12, L))
+    log("input state: 12 ciphertexts per (N, level) in use ...")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    for ln, k, level in mix:
+        if (ln, level) not in pools:
+            q = torch.tensor(prms[ln].q[:level], dtype=torch.int64, device="cuda").view(1, 1, level, 1)
+            r = torch.randint(0, 1 << 62, (12, 2, level, 1 << ln), generator=gen, device="cuda", dtype=torch.int64)
+            pools[(ln, level)] = (r % q).to(torch.int32)
+            del r
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    resident = free0 - torch.cuda.mem_get_info()[0]
+    log("resident keys + input state: %.2f GB" % (resident / 1e9))
+
+    def requests(arrivals):
+        out = []
+        for i, ((ln, k, level), t) in enumerate(zip(mix, arrivals)):
+            out.append(serve.Request(i, ln, k, level, t, inputs=[pools[(ln, level)][u] for u in range(k)]))
+        return out
+
+    check = set(range(0, n_req, 97))
+    ex = serve.GpuExecutor(mick, torch, prms, keys, n_streams=args.serve_streams, keep=lambda r: r.rid in check)
+    srv = serve.Server(ex, budget, resident=resident, max_batch=args.serve_max_batch)
+    log("warmup ...")
+    ex.start()
+    srv.run(requests([0.0] * n_req)[:64])
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    reserved0 = torch.cuda.memory_reserved()
+    log("saturation: %d requests at t = 0 ..." % n_req)
+    ex.start()
+    sat = srv.run(requests([0.0] * n_req))
+    sat_rate = sat.summary()["ct_mults_per_s"]
+    log("  %s host launch %.3f s" % (sat.summary(), ex.host_launch_s))
+    results = []
+    for frac, seed in ((0.5, 50), (0.8, 51), (0.95, 52)):
+        rate = frac * sat_rate
+        log("open loop at %.2f x saturation = %.0f requests/s ..." % (frac, rate))
+        ex.start()
+        st = srv.run(requests(serve.poisson_arrivals(n_req, rate, seed)))
+        summ = st.summary()
+        summ["host_launch_s"] = round(ex.host_launch_s, 3)
+        heavy = [r.done - r.arrival for r in st.completed if r.k == 12 and r.log_n == 16]
+        light = [r.done - r.arrival for r in st.completed if r.log_n < 16]
+        summ.update({"offered_per_s": round(rate, 1), "load": frac,
+                     "p99_heavy_ms": round(float(np.percentile(heavy, 99)) * 1e3, 3) if heavy else None,
+                     "p99_light_ms": round(float(np.percentile(light, 99)) * 1e3, 3) if light else None})
+        log("  %s" % summ)
+        results.append(summ)
+    torch.cuda.synchronize()
+    peak_hbm = resident + torch.cuda.max_memory_reserved() - reserved0
+    # each sampled request's served output equals the same multiply launched alone
+    kept = [r for r in st.completed if r.rid in check]
+    for r in kept:
+        o = mick.mul_relin_rescale(prms[r.log_n], keys[r.log_n], r.inputs, r.level)
+        assert torch.equal(o, r.output), "request %d differs from its plain multiply" % r.rid
+    log("alone == in the mix for %d sampled requests" % len(kept))
+    # plain: every request of a 500-request sample launched alone, back to back
+    sample = requests([0.0] * n_req)[:500]
+    wss = {ln: mick.workspace(prms[ln], mick.OP_MUL_RELIN_RESCALE, min(12, MIXED_PARAMS[ln][0]),
+                              MIXED_PARAMS[ln][0]) for ln in prms}
+    outs = [torch.empty(2, r.level - r.k + 1, 1 << r.log_n, dtype=torch.int32, device="cuda") for r in sample]
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for rep in range(2):
+        e0.record(stream)
+        for r, o in zip(sample, outs):
+            mick.mul_relin_rescale(prms[r.log_n], keys[r.log_n], r.inputs, r.level, out=o, ws=wss[r.log_n])
+        e1.record(stream)
+        torch.cuda.synchronize()
+    plain_rate = len(sample) / (e0.elapsed_time(e1) / 1e3)
+    log("plain: %.1f ct-mults/s over the first %d requests" % (plain_rate, len(sample)))
+    top = results[-1]
+    rec = {
+        "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
+        "value": top["ct_mults_per_s"], "unit": "ct-mults/s", "n_gpus": 1, "steps": n_req, "warmup": 64,
+        "ms_per_step": round(1e3 / top["ct_mults_per_s"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "serving: 5000 requests, open-loop Poisson at 0.95 x measured saturation, mixed N "
+                               "2^13..2^16 with 10%% heavy (N=2^16, k=12), HBM budget %d GB" % (budget // 10 ** 9),
+                   "batch": "continuous", "max_batch": args.serve_max_batch, "streams": args.serve_streams,
+                   "parallelism": "none"},
+        "saturation_per_s": sat_rate,
+        "rates": results,
+        "latency_ms": {"p50": top["p50_ms"], "p99": top["p99_ms"], "of": "one request, arrival to completion"},
+        "plain": {"value": round(plain_rate, 2), "unit": "ct-mults/s", "sample": "first 500 requests, each alone"},
+        "served_over_plain": round(top["ct_mults_per_s"] / plain_rate, 3),
+        "saturation_over_plain": round(sat_rate / plain_rate, 3),
+        "hbm": {"budget_gb": budget / 1e9, "resident_gb": round(resident / 1e9, 3),
+                "peak_gb": round(peak_hbm / 1e9, 3), "device_gb": round(total / 1e9, 1)},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +417,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--serve-streams", type=int, default=2, help="serve5000: concurrent micro-batches")
+    ap.add_argument("--serve-max-batch", type=int, default=256, help="serve5000: most requests per micro-batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized buffer once before timing (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -318,6 +432,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "mixed512":
         run_mixed(args, torch, mick)
+        return
+    if args.workload == "serve5000":
+        run_serve(args, torch, mick)
         return
     log_n, L, K, dnum, k, level, jobs = WORKLOADS[args.workload]
     log("params N=2^%d L=%d K=%d dnum=%d; keygen k_max=%d ..." % (log_n, L, K, dnum, k))

@@ -312,6 +312,18 @@ def make_jobs(prm: Params, specs):
     return arr, outs
 
 
+def jobs_workspace_bytes(prm: Params, shapes) -> int:
+    """Workspace of a job table holding jobs of the given (k, level) shapes
+    (pointers are not needed to size it)."""
+    arr = (Job * len(shapes))()
+    for i, (k, level) in enumerate(shapes):
+        arr[i].k, arr[i].level = k, level
+    nbytes = load().mick_jobs_workspace_bytes(prm.handle, ctypes.cast(arr, _vp), len(arr))
+    if nbytes == 0:
+        raise ValueError("invalid job shapes")
+    return nbytes
+
+
 def jobs_workspace(prm: Params, arr) -> torch.Tensor:
     nbytes = load().mick_jobs_workspace_bytes(prm.handle, ctypes.cast(arr, _vp), len(arr))
     if nbytes == 0:
