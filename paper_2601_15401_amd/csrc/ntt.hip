@@ -332,26 +332,47 @@ void launch_pass(int logr, dim3 grid, hipStream_t s, const uint32_t* src, uint32
 // sum of ALPHA <= 8 products of a residue below 2^30 and a constant below m
 // stays below 2m 2^32, so one Montgomery reduction returns it mod m.
 template <int LOGR, int ALPHA, bool LAZY>
-__device__ __forceinline__ void modup_a_body(const uint32_t* const (&srow)[ALPHA], const uint32_t (&cc)[ALPHA],
+__device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na, const uint32_t (&cc)[ALPHA],
                                              uint32_t minv, uint32_t* dst, uint32_t* lds, int H, int col0,
                                              uint32_t q, const uint2* tw) {
   using G = Geo<LOGR>;
   using R1 = Rnd<LOGR, false, true>;
   using R2 = Rnd<LOGR, false, false>;
   const uint4 nf{};
+  // the item's rows are 2^NLO_LOG rows apart: a uniform byte step per j
+  constexpr uint32_t kRowStep = 4u << R1::NLO_LOG;
+  const uint32_t row_bytes = 4u << (H + LOGR);  // one source limb
 #pragma unroll
   for (int i = 0; i < R1::NI; i++) {
     int c, rb, hi;
     R1::decode(i * kThreads + threadIdx.x, c, rb, hi);
+    const uint32_t voff = 4u * R1::gidx(H, col0 + c, R1::row(rb, 0));
+    uint32_t vj[R1::E];  // lane offsets of the item's positions in one limb
+#pragma unroll
+    for (int j = 0; j < R1::E; j++) vj[j] = voff + ((uint32_t)j * kRowStep << H);
+    uint64_t acc[R1::E];
+#pragma unroll
+    for (int j = 0; j < R1::E; j++) acc[j] = 0;
+    // source row outermost, double-buffered: the E independent loads of row
+    // a + 1 are in flight while row a is accumulated (padded rows reread a
+    // valid limb and are multiplied by 0)
+    uint32_t v[2][R1::E];
+#pragma unroll
+    for (int j = 0; j < R1::E; j++) v[0][j] = __builtin_amdgcn_raw_buffer_load_b32(src, vj[j], 0, 0);
+#pragma unroll
+    for (int a = 0; a < ALPHA; a++) {
+      if (a + 1 < ALPHA) {
+        const uint32_t soff = (uint32_t)min(a + 1, na - 1) * row_bytes;
+#pragma unroll
+        for (int j = 0; j < R1::E; j++)
+          v[(a + 1) & 1][j] = __builtin_amdgcn_raw_buffer_load_b32(src, vj[j], soff, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < R1::E; j++) acc[j] += (uint64_t)v[a & 1][j] * cc[a];
+    }
     uint32_t x[R1::E];
 #pragma unroll
-    for (int j = 0; j < R1::E; j++) {
-      const uint32_t g = R1::gidx(H, col0 + c, R1::row(rb, j));
-      uint64_t acc = 0;
-#pragma unroll
-      for (int a = 0; a < ALPHA; a++) acc += (uint64_t)srow[a][g] * cc[a];
-      x[j] = redc_2m(acc, q, minv);
-    }
+    for (int j = 0; j < R1::E; j++) x[j] = redc_2m(acc[j], q, minv);
     item_bfly<R1::RB, true, LAZY, false>(x, tw, R1::SL0, 0, hi, 0, q, nf);
     store_lds<R1, G::PAD>(x, lds, c, rb);
   }
@@ -365,6 +386,12 @@ __device__ __forceinline__ void modup_a_body(const uint32_t* const (&srow)[ALPHA
     item_bfly<R2::RB, true, LAZY, false>(x, tw, R2::SL0, 0, hi, 0, q, nf);
     store_global<R2>(x, dst, H, col0 + c, rb);
   }
+}
+
+// Raw buffer descriptor over `bytes` bytes at `base` (gfx9 word 3: 32-bit
+// data format, no swizzle, no stride).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
 template <int LOGR, int ALPHA>
@@ -389,20 +416,17 @@ __global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint3
   // [ALPHA][E] qhat_j R mod m_e, zero rows padded
   const uint32_t* C = A.tab + A.tab_off[b] + 2 * ALPHA;
   const uint32_t* base = dsc + (size_t)job * (size_t)A.dcoef_job + ((size_t)t2 * A.level + lo) * N;
-  const uint32_t* srow[ALPHA];
+  const __amdgpu_buffer_rsrc_t src = buffer_rsrc(base, (uint32_t)(na * N * 4));
   uint32_t cc[ALPHA];
 #pragma unroll
-  for (int a = 0; a < ALPHA; a++) {
-    srow[a] = base + (size_t)min(a, na - 1) * N;  // padded rows read a valid limb, times 0
-    cc[a] = C[a * A.E + e];
-  }
+  for (int a = 0; a < ALPHA; a++) cc[a] = C[a * A.E + e];
   uint32_t* dst = X + (size_t)job * (size_t)A.x_job + ((size_t)tb * A.E + e) * N;
   const int H = A.log_n - LOGR;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    modup_a_body<LOGR, ALPHA, true>(srow, cc, minv, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, true>(src, na, cc, minv, dst, lds, H, col0, q, tw);
   else
-    modup_a_body<LOGR, ALPHA, false>(srow, cc, minv, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, false>(src, na, cc, minv, dst, lds, H, col0, q, tw);
 }
 
 // ------------------------------------------------------------------ pass B + key inner product
@@ -627,20 +651,17 @@ __global__ __launch_bounds__(kThreads) void k_modup_a_jt(const JobDesc* jt, int 
   const WsLayout lay(k, level, G.K, G.alpha, log_n);
   const uint32_t* C = G.modup_tab + G.modup_off[(level - 1) * G.dnum + b] + 2 * ALPHA;
   const uint32_t* base = jt[j].ws + lay.dcoef + ((size_t)t2 * level + lo) * N;
-  const uint32_t* srow[ALPHA];
+  const __amdgpu_buffer_rsrc_t src = buffer_rsrc(base, (uint32_t)(na * N * 4));
   uint32_t cc[ALPHA];
 #pragma unroll
-  for (int a = 0; a < ALPHA; a++) {
-    srow[a] = base + (size_t)min(a, na - 1) * N;
-    cc[a] = C[a * E + e];
-  }
+  for (int a = 0; a < ALPHA; a++) cc[a] = C[a * E + e];
   uint32_t* dst = jt[j].ws + lay.X + ((size_t)tb * E + e) * N;
   const int H = log_n - LOGR;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    modup_a_body<LOGR, ALPHA, true>(srow, cc, minv, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, true>(src, na, cc, minv, dst, lds, H, col0, q, tw);
   else
-    modup_a_body<LOGR, ALPHA, false>(srow, cc, minv, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, false>(src, na, cc, minv, dst, lds, H, col0, q, tw);
 }
 
 // Pass B + key inner product over the jobs of a table.  Blocks per job:
