@@ -55,7 +55,9 @@ def site_work(site, N, k, level, K, alpha, jobs):
     Bytes: every input element read once and every output element written once
     (4 bytes each); key material counted once per launch.  Ops: a radix-2
     butterfly mod q is counted as 9 VALU operations (Shoup product 4, lazy
-    reduction 2, add 1, subtract-and-offset 2)."""
+    reduction 2, add 1, subtract-and-offset 2); a key product accumulated into
+    an exact 96-bit sum as 2 (multiply-add, carry) and each such sum's final
+    reduction mod q as 30."""
     E = level + K
     B = -(-level // alpha)
     mu = k - 1
@@ -72,7 +74,7 @@ def site_work(site, N, k, level, K, alpha, jobs):
         x = jobs * (new_limbs + (k - 1) * level)
         keys = (k - 1) * B * 2 * E
         return limb * (x + keys + jobs * 2 * level + jobs * 2 * E), \
-            jobs * (new_limbs * (N / 2) * 8 * bfly + (k - 1) * B * E * N * 2 * 9.0)
+            jobs * (new_limbs * (N / 2) * 8 * bfly + (k - 1) * B * E * N * 2 * 2.0 + 2 * E * N * 30.0)
     if site.startswith("intt_d"):
         n = jobs * (k - 1) * level
         return 2 * limb * n, n * (N / 2) * 8 * bfly

@@ -52,6 +52,16 @@ __device__ __forceinline__ uint32_t redc_2m(uint64_t T, uint32_t m, uint32_t min
   return hi < mh ? r + m : red1(r, m);
 }
 
+// (hi, lo) += a * b on a 96-bit accumulator: one 32x32+64-bit multiply-add
+// whose carry-out goes to a lane mask, and one add of that carry into hi.
+__device__ __forceinline__ void mac96(uint64_t& lo, uint32_t& hi, uint32_t a, uint32_t b) {
+  uint64_t carry;
+  asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
+      "v_addc_co_u32_e64 %2, %1, 0, %2, %1"
+      : "+v"(lo), "=&s"(carry), "+v"(hi)
+      : "v"(a), "v"(b));
+}
+
 // Per-modulus constants for reducing a full 64-bit value.
 struct Red64 {
   uint32_t m;

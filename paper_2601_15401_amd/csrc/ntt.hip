@@ -448,10 +448,12 @@ struct TwLds {
 template <int LOGR, bool LAZY>
 __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* De, const uint32_t* evk_e,
                                            uint32_t* acc_e, const KipArgs& A, uint32_t* lds, uint2* ltw, int e,
-                                           int col0, uint32_t q, uint32_t minv, const uint2* tw) {
+                                           int col0, uint32_t q, uint32_t minv, const Red64& red, const uint2* tw) {
   using G = Geo<LOGR>;
   using R1 = Rnd<LOGR, true, true, kKipThreads>;
   using R2 = Rnd<LOGR, true, false, kKipThreads>;
+  constexpr int V = R1::NI * R1::E;  // words of the tile held by one thread
+  static_assert(V == R2::NI * R2::E, "both rounds cover the tile");
   const size_t N = (size_t)1 << A.log_n;
   const int s0 = A.log_n - LOGR;
   const uint4 nf{};
@@ -463,76 +465,148 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
     const int rr = k + 1 - (1 << sl);
     ltw[i] = tw[(1 << (s0 + sl)) + (rr << s0) + col0 + c];
   }
-  __syncthreads();
-  uint32_t a0[R2::NI][R2::E], a1[R2::NI][R2::E];
-#pragma unroll
-  for (int i = 0; i < R2::NI; i++)
-#pragma unroll
-    for (int j = 0; j < R2::E; j++) a0[i][j] = a1[i][j] = 0;
-  for (int t = 2; t <= A.k; t++) {
-    for (int b = 0; b < A.B; b++) {
-      const int lo = b * A.alpha;
-      const bool own = e >= lo && e < min(lo + A.alpha, A.level);
-      const uint32_t* k0p = evk_e + (((size_t)(t - 2) * A.dnum + b) * 2) * (size_t)A.key_poly;
-      const uint32_t* k1p = k0p + A.key_poly;
-      if (!own) {
-        const uint32_t* src = Xe + (((size_t)(t - 2) * A.B + b) * A.E) * N;
-#pragma unroll
-        for (int i = 0; i < R1::NI; i++) {
-          int c, rb, hi;
-          R1::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
-          uint32_t x[R1::E];
-          load_global<R1>(x, src, 0, col0 + c, rb);
-          item_bfly_t<R1::RB, true, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, c}, s0 + R1::SL0, hi, q, nf);
-          store_lds<R1, G::PAD>(x, lds, c, rb);
-        }
-        __syncthreads();
-      }
+  // pairs p = (t - 2) B + b.  A pair is "own" when limb e belongs to digit b:
+  // its ModUp image is D_t itself (NTT domain, round-2 layout); otherwise the
+  // pass-A output X_{t,b,e} is read in round-1 layout.
+  const int P = (A.k - 1) * A.B;
+  auto own_of = [&](int p) {
+    const int lo = (p % A.B) * A.alpha;
+    return e >= lo && e < min(lo + A.alpha, A.level);
+  };
+  // the transform input of one pair
+  auto fetch_x = [&](int p, uint32_t (&xv)[V]) {
+    if (own_of(p)) {
+      const uint32_t* d = De + (size_t)(p / A.B + 2) * A.level * N;
 #pragma unroll
       for (int i = 0; i < R2::NI; i++) {
         int c, rb, hi;
         R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
         uint32_t x[R2::E];
-        if (own) {
-          load_global<R2>(x, De + (size_t)t * A.level * N, 0, col0 + c, rb);  // D_t, NTT domain
-        } else {
-          load_lds<R2, G::PAD>(x, lds, c, rb);
-          item_bfly_t<R2::RB, true, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, c}, s0 + R2::SL0, hi, q, nf);
-        }
-        const uint32_t g = R2::gidx(0, col0 + c, rb);
+        load_global<R2>(x, d, 0, col0 + c, rb);
 #pragma unroll
-        for (int j = 0; j < R2::E; j += 4) {
-          const uint4 k0 = *reinterpret_cast<const uint4*>(k0p + g + j);
-          const uint4 k1 = *reinterpret_cast<const uint4*>(k1p + g + j);
-          a0[i][j] = add_mod(a0[i][j], mont_mul(x[j], k0.x, q, minv), q);
-          a0[i][j + 1] = add_mod(a0[i][j + 1], mont_mul(x[j + 1], k0.y, q, minv), q);
-          a0[i][j + 2] = add_mod(a0[i][j + 2], mont_mul(x[j + 2], k0.z, q, minv), q);
-          a0[i][j + 3] = add_mod(a0[i][j + 3], mont_mul(x[j + 3], k0.w, q, minv), q);
-          a1[i][j] = add_mod(a1[i][j], mont_mul(x[j], k1.x, q, minv), q);
-          a1[i][j + 1] = add_mod(a1[i][j + 1], mont_mul(x[j + 1], k1.y, q, minv), q);
-          a1[i][j + 2] = add_mod(a1[i][j + 2], mont_mul(x[j + 2], k1.z, q, minv), q);
-          a1[i][j + 3] = add_mod(a1[i][j + 3], mont_mul(x[j + 3], k1.w, q, minv), q);
-        }
+        for (int j = 0; j < R2::E; j++) xv[i * R2::E + j] = x[j];
       }
-      if (!own) __syncthreads();  // the next pair's first round rewrites the tile
+    } else {
+      const uint32_t* src = Xe + (size_t)p * A.E * N;
+#pragma unroll
+      for (int i = 0; i < R1::NI; i++) {
+        int c, rb, hi;
+        R1::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+        uint32_t x[R1::E];
+        load_global<R1>(x, src, 0, col0 + c, rb);
+#pragma unroll
+        for (int j = 0; j < R1::E; j++) xv[i * R1::E + j] = x[j];
+      }
+    }
+  };
+  // both key words of every round-2 position of this thread
+  auto fetch_k = [&](int p, uint4 (&kv)[V / 2]) {
+    const int t2 = p / A.B, b = p - t2 * A.B;
+    const uint32_t* k0p = evk_e + (((size_t)t2 * A.dnum + b) * 2) * (size_t)A.key_poly;
+    const uint32_t* k1p = k0p + A.key_poly;
+#pragma unroll
+    for (int i = 0; i < R2::NI; i++) {
+      int c, rb, hi;
+      R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+      const uint32_t g = R2::gidx(0, col0 + c, rb);
+#pragma unroll
+      for (int j = 0; j < R2::E; j += 4) {
+        kv[(i * R2::E + j) / 2] = *reinterpret_cast<const uint4*>(k0p + g + j);
+        kv[(i * R2::E + j) / 2 + 1] = *reinterpret_cast<const uint4*>(k1p + g + j);
+      }
+    }
+  };
+  // exact sums of the products (each below 2^63) in 96 bits; reduced once
+  uint64_t l0[V], l1[V];
+  uint32_t h0[V], h1[V];
+#pragma unroll
+  for (int j = 0; j < V; j++) {
+    l0[j] = l1[j] = 0;
+    h0[j] = h1[j] = 0;
+  }
+  uint32_t xn[V];
+  fetch_x(0, xn);
+  __syncthreads();  // twiddles staged
+  int buf = 0;
+  for (int p = 0; p < P; p++) {
+    const bool own = own_of(p);
+    uint32_t x[V];
+#pragma unroll
+    for (int j = 0; j < V; j++) x[j] = xn[j];
+    // key words of this pair arrive while it is transformed; the next pair's
+    // input arrives during this whole iteration
+    uint4 kk[V / 2];
+    fetch_k(p, kk);
+    if (p + 1 < P) fetch_x(p + 1, xn);
+    if (!own) {
+      // two tile buffers: the next pair's first round may write the other
+      // buffer while slower threads still read this one, so one barrier per
+      // pair suffices
+      uint32_t* tile = lds + buf * G::LDS_WORDS;
+#pragma unroll
+      for (int i = 0; i < R1::NI; i++) {
+        int c, rb, hi;
+        R1::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+        uint32_t y[R1::E];
+#pragma unroll
+        for (int j = 0; j < R1::E; j++) y[j] = x[i * R1::E + j];
+        item_bfly_t<R1::RB, true, LAZY, false>(y, TwLds<G::COLS>{ltw, s0, c}, s0 + R1::SL0, hi, q, nf);
+        store_lds<R1, G::PAD>(y, tile, c, rb);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < R2::NI; i++) {
+        int c, rb, hi;
+        R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+        uint32_t y[R2::E];
+        load_lds<R2, G::PAD>(y, tile, c, rb);
+        item_bfly_t<R2::RB, true, LAZY, false>(y, TwLds<G::COLS>{ltw, s0, c}, s0 + R2::SL0, hi, q, nf);
+#pragma unroll
+        for (int j = 0; j < R2::E; j++) x[i * R2::E + j] = y[j];
+      }
+      buf ^= 1;
+    }
+#pragma unroll
+    for (int j = 0; j < V; j += 4) {
+      const uint4 k0 = kk[j / 2], k1 = kk[j / 2 + 1];
+      mac96(l0[j], h0[j], x[j], k0.x);
+      mac96(l0[j + 1], h0[j + 1], x[j + 1], k0.y);
+      mac96(l0[j + 2], h0[j + 2], x[j + 2], k0.z);
+      mac96(l0[j + 3], h0[j + 3], x[j + 3], k0.w);
+      mac96(l1[j], h1[j], x[j], k1.x);
+      mac96(l1[j + 1], h1[j + 1], x[j + 1], k1.y);
+      mac96(l1[j + 2], h1[j + 2], x[j + 2], k1.z);
+      mac96(l1[j + 3], h1[j + 3], x[j + 3], k1.w);
     }
   }
+  // sum mod q, then the key's factor R = 2^32 removed by one Montgomery step
+  const uint32_t r32 = red.r32, r32sh = red.r32sh;
+  auto finish = [&](uint64_t lo, uint32_t hi) {
+    const uint32_t th = shoup(shoup(hi, r32, r32sh, q), r32, r32sh, q);  // hi 2^64 mod q
+    return mont_mul(add_mod(reduce64(lo, red), th, q), 1u, q, minv);
+  };
 #pragma unroll
   for (int i = 0; i < R2::NI; i++) {
     int c, rb, hi;
     R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+    uint32_t o0[R2::E], o1[R2::E];
+#pragma unroll
+    for (int j = 0; j < R2::E; j++) {
+      o0[j] = finish(l0[i * R2::E + j], h0[i * R2::E + j]);
+      o1[j] = finish(l1[i * R2::E + j], h1[i * R2::E + j]);
+    }
     if (e < A.level) {  // relocated ModDown input D_l + P^-1 C~ on the q rows
       uint32_t d0[R2::E], d1[R2::E];
       load_global<R2>(d0, De, 0, col0 + c, rb);
       load_global<R2>(d1, De + (size_t)A.level * N, 0, col0 + c, rb);
 #pragma unroll
       for (int j = 0; j < R2::E; j++) {
-        a0[i][j] = add_mod(a0[i][j], d0[j], q);
-        a1[i][j] = add_mod(a1[i][j], d1[j], q);
+        o0[j] = add_mod(o0[j], d0[j], q);
+        o1[j] = add_mod(o1[j], d1[j], q);
       }
     }
-    store_global<R2>(a0[i], acc_e, 0, col0 + c, rb);
-    store_global<R2>(a1[i], acc_e + (size_t)A.E * N, 0, col0 + c, rb);
+    store_global<R2>(o0, acc_e, 0, col0 + c, rb);
+    store_global<R2>(o1, acc_e + (size_t)A.E * N, 0, col0 + c, rb);
   }
 }
 
@@ -541,7 +615,7 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
 template <int LOGR>
 __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const uint32_t* D, const uint32_t* evk,
                                                        uint32_t* acc, KipArgs A, DevTables T) {
-  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  __shared__ uint32_t lds[2 * Geo<LOGR>::LDS_WORDS];
   __shared__ uint2 ltw[Geo<LOGR>::COLS * ((1 << LOGR) - 1)];
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
   const int job = seq % A.n_jobs;
@@ -559,9 +633,9 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
   uint32_t* acc_e = acc + (size_t)job * (size_t)A.acc_job + (size_t)e * N;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    kip_b_body<LOGR, true>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, tw);
+    kip_b_body<LOGR, true>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, T.red[pe], tw);
   else
-    kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, tw);
+    kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, T.red[pe], tw);
 }
 
 // ------------------------------------------------------------------ job-table forms
@@ -668,7 +742,7 @@ __global__ __launch_bounds__(kThreads) void k_modup_a_jt(const JobDesc* jt, int 
 // ceil(E tiles / 8) 8.
 template <int LOGR>
 __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
-  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  __shared__ uint32_t lds[2 * Geo<LOGR>::LDS_WORDS];
   __shared__ uint2 ltw[Geo<LOGR>::COLS * ((1 << LOGR) - 1)];
   const int j = find_job(jt, nj, S_KIP, blockIdx.x);
   const int local = blockIdx.x - jt[j].blk0[S_KIP];
@@ -699,10 +773,10 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
     kip_b_body<LOGR, true>(ws + lay.X + (size_t)e * N, ws + lay.D + (size_t)e * N, G.evk + (size_t)pe * N,
-                           ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, tw);
+                           ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, T.red[pe], tw);
   else
     kip_b_body<LOGR, false>(ws + lay.X + (size_t)e * N, ws + lay.D + (size_t)e * N, G.evk + (size_t)pe * N,
-                            ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, tw);
+                            ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, T.red[pe], tw);
 }
 
 template <bool FWD, bool PASSB>
