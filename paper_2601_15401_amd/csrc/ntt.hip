@@ -54,9 +54,14 @@ template <int LOGR>
 struct Geo {
   static constexpr int LOGC = kTileLog - LOGR;
   static constexpr int COLS = 1 << LOGC;
-  static constexpr int PAD = COLS + 1;
   static constexpr int RB0 = (LOGR == 6) ? 3 : 4;
   static constexpr int RB1 = LOGR - RB0;
+  // LDS row pitch.  Pass B's strided round gives each column 2^(LOGR-RB0)
+  // consecutive lanes (rows lo, lo + 2^(LOGR-RB0), ...), so a 32-lane half
+  // touches 32 >> (LOGR-RB0) columns; a pitch of COLS + that count puts
+  // their lanes on distinct banks.  Every other round has 32 consecutive
+  // columns of one row per half, conflict-free at any pitch.
+  static constexpr int PAD = COLS + (32 >> (LOGR - RB0));
   static constexpr int LDS_WORDS = (1 << LOGR) * PAD;
 };
 
@@ -203,12 +208,17 @@ __device__ __forceinline__ void item_bfly(uint32_t (&x)[1 << RB], const uint2* t
   item_bfly_t<RB, FWD, LAZY, HAS_STAGE0>(x, TwGlobal{tw, s0, blk}, s_first, hi, q, nfix);
 }
 
-template <typename RD>
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Global accesses of one item.  STREAM marks data touched once per pass
+// (nontemporal: it should not displace the twiddles other tiles reuse).
+template <typename RD, bool STREAM = false>
 __device__ __forceinline__ void load_global(uint32_t (&x)[RD::E], const uint32_t* g, int H, int col, int rbase) {
   if constexpr (RD::VEC) {
 #pragma unroll
     for (int j = 0; j < RD::E; j += 4) {
-      const uint4 v = *reinterpret_cast<const uint4*>(g + RD::gidx(H, col, rbase + j));
+      const u32x4* p = reinterpret_cast<const u32x4*>(g + RD::gidx(H, col, rbase + j));
+      const u32x4 v = STREAM ? __builtin_nontemporal_load(p) : *p;
       x[j] = v.x;
       x[j + 1] = v.y;
       x[j + 2] = v.z;
@@ -216,25 +226,38 @@ __device__ __forceinline__ void load_global(uint32_t (&x)[RD::E], const uint32_t
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < RD::E; j++) x[j] = g[RD::gidx(H, col, RD::row(rbase, j))];
+    for (int j = 0; j < RD::E; j++) {
+      const uint32_t* p = g + RD::gidx(H, col, RD::row(rbase, j));
+      x[j] = STREAM ? __builtin_nontemporal_load(p) : *p;
+    }
   }
 }
 
-template <typename RD>
+template <typename RD, bool STREAM = false>
 __device__ __forceinline__ void store_global(const uint32_t (&x)[RD::E], uint32_t* g, int H, int col, int rbase) {
   if constexpr (RD::VEC) {
 #pragma unroll
     for (int j = 0; j < RD::E; j += 4) {
-      uint4 o;
+      u32x4 o;
       o.x = x[j];
       o.y = x[j + 1];
       o.z = x[j + 2];
       o.w = x[j + 3];
-      *reinterpret_cast<uint4*>(g + RD::gidx(H, col, rbase + j)) = o;
+      u32x4* p = reinterpret_cast<u32x4*>(g + RD::gidx(H, col, rbase + j));
+      if constexpr (STREAM)
+        __builtin_nontemporal_store(o, p);
+      else
+        *p = o;
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < RD::E; j++) g[RD::gidx(H, col, RD::row(rbase, j))] = x[j];
+    for (int j = 0; j < RD::E; j++) {
+      uint32_t* p = g + RD::gidx(H, col, RD::row(rbase, j));
+      if constexpr (STREAM)
+        __builtin_nontemporal_store(x[j], p);
+      else
+        *p = x[j];
+    }
   }
 }
 
