@@ -226,6 +226,89 @@ int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job
 int mick_plan_execute(const mick_plan* plan, void* stream);
 void mick_plan_destroy(mick_plan* plan);
 
+/* ---------------------------------------------------------------- work queue
+ * A host-driven queue of multiplies over one or more parameter sets (for
+ * instance the four ring degrees of a mixed workload), with admission by
+ * device memory.  The queue owns one device workspace arena of `capacity`
+ * bytes (from the registered allocator), allocated at creation.
+ *
+ *  - mick_queue_push appends jobs (all or none: any invalid job rejects the
+ *    call) to a FIFO; it launches nothing.
+ *  - mick_queue_run admits pending jobs in FIFO order while the workspace of
+ *    each fits a free block of the arena (first fit; it stops at the first
+ *    job that does not fit, so admission stays in arrival order), groups the
+ *    admitted jobs by parameter set and launches each group as one job-table
+ *    plan (see mick_jobs_plan) on `stream`, smaller ring degrees first, each
+ *    group followed by its own completion event.  It returns the number of
+ *    jobs launched (0 if none fitted or none were pending) and does not wait.
+ *  - mick_queue_poll writes the ids of completed jobs (at most max) to
+ *    done_ids, returns their number and frees their workspace.  Completion
+ *    follows each group's event, so groups launched on different streams may
+ *    complete in any order.
+ *  - mick_queue_drain runs and polls until every pushed job has completed,
+ *    waiting on the oldest running group whenever nothing more fits; the
+ *    ids of the jobs it completes are discarded (poll first to keep them).
+ *  - mick_queue_info reports pending jobs, running jobs and arena bytes in
+ *    use (any pointer may be NULL).
+ *  - mick_queue_destroy (NULL-safe) waits for running groups, then frees the
+ *    arena.
+ * The queue keeps the jobs' ciphertext and output pointers until they
+ * complete; the caller keeps those buffers, the parameter sets and the keys
+ * alive meanwhile.  A queue is driven by one host thread at a time.
+ * Results are bit-identical to mick_mul_relin_rescale of each job alone. */
+typedef struct mick_queue mick_queue;
+
+typedef struct mick_qjob {
+  uint64_t id;               /* caller's tag, returned by mick_queue_poll */
+  int set;                   /* index into the queue's parameter sets */
+  int k;                     /* 2..12, at most that set's key k_max */
+  int level;                 /* k..L of that set */
+  const uint32_t* cts[12];   /* k device pointers, uint32[2][level][N] each */
+  uint32_t* out;             /* device uint32[2][level-k+1][N] */
+} mick_qjob;
+
+/* prms, keys: host arrays of n_sets (1..16) handles, keys[i] generated for
+ * prms[i].  capacity: arena bytes; a job whose workspace alone exceeds it is
+ * rejected by mick_queue_push. */
+int mick_queue_create(const mick_params* const* prms, const mick_keys* const* keys, int n_sets, size_t capacity,
+                      mick_queue** out);
+/* Device workspace one job holds while it runs (what admission counts). */
+size_t mick_queue_job_bytes(const mick_queue* q, int set, int k, int level);
+int mick_queue_push(mick_queue* q, const mick_qjob* jobs, int n_jobs);
+int mick_queue_run(mick_queue* q, void* stream);
+int mick_queue_poll(mick_queue* q, uint64_t* done_ids, int max);
+int mick_queue_drain(mick_queue* q, void* stream);
+int mick_queue_info(const mick_queue* q, int* pending, int* running, size_t* bytes_in_use);
+void mick_queue_destroy(mick_queue* q);
+
+/* ---------------------------------------------------------------- schedule
+ * The transform splits log N into a first pass over 2^a rows and a second
+ * over 2^(log N - a); the fused ModUp kernels exist for a in {7, 8} and
+ * second passes of 6..8 stages, so N = 2^14 and 2^15 have two schedules
+ * (N = 2^13: a = 7; N = 2^16: a = 8).  mick_autotune times the forward and
+ * inverse transforms of L + K limbs under each schedule on the current
+ * device and keeps the fastest; with a cache file it first looks up the
+ * (device, N, L, K, dnum) entry and appends the result after timing (NULL:
+ * the path in the environment variable MICK_AUTOTUNE_CACHE, else no cache).
+ * Changing the schedule rebuilds the parameter tables (device work,
+ * synchronous): call it before keys are generated or jobs are queued with
+ * these parameters, never while work using them is in flight.
+ * mick_params_schedule reports the first-pass log size a. */
+int mick_autotune(mick_params* prm, const char* cache_path);
+int mick_params_set_schedule(mick_params* prm, int first_pass_log);
+int mick_params_schedule(const mick_params* prm);
+
+/* ---------------------------------------------------------------- allocator
+ * Device memory of the library's own objects (parameter tables, keys,
+ * queue arenas, temporary buffers of encryption and decryption) comes from
+ * this allocator; by default hipMalloc / hipFree.  alloc(bytes, ctx) returns
+ * device memory aligned to 256 bytes or NULL; release(ptr, ctx) frees it.
+ * Process-wide; each object keeps the pair in force at its creation and
+ * frees its memory with it.  Pass NULL, NULL to restore the default. */
+typedef void* (*mick_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*mick_free_fn)(void* ptr, void* ctx);
+int mick_set_allocator(mick_alloc_fn alloc, mick_free_fn release, void* ctx);
+
 /* Forward / inverse negacyclic NTT of n_limbs limbs in place, limb i taken
  * mod prime index first_prime + i (prime index j < L is q_j, L + i is p_i).
  * Exposed for testing and benchmarking of the transform itself. */

@@ -1,5 +1,7 @@
 // C ABI of libmick: parameter tables, key generation, encryption,
 // decryption and the orchestration of the k-input multiply.
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -67,13 +69,6 @@ namespace {
 constexpr int kSecretWeight = 64;
 constexpr double kSigma = 3.2;
 
-#define MICK_TRY(expr)            \
-  do {                            \
-    int _st = (expr);             \
-    if (_st != MICK_OK) return _st; \
-  } while (0)
-
-#define MICK_HIP(expr, what) MICK_TRY(hip_error((expr), (what)))
 
 uint32_t inv_pow2_32(uint32_t m) {  // m^-1 mod 2^32 by Newton iteration
   uint32_t x = m;
@@ -95,9 +90,10 @@ int upload(T* dst, const std::vector<T>& src, hipStream_t s) {
 }
 
 template <typename T>
-int dev_alloc(T** p, size_t count) {
-  hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
-  if (e != hipSuccess) return set_error(MICK_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+int dev_alloc(const Allocator& a, T** p, size_t count) {
+  void* v = nullptr;
+  MICK_TRY(dev_alloc_bytes(a, &v, std::max<size_t>(count, 1) * sizeof(T)));
+  *p = (T*)v;
   return MICK_OK;
 }
 
@@ -181,7 +177,7 @@ int build_tables(mick_params* prm) {
       rp = rp * R % m;
     }
   }
-  MICK_TRY(dev_alloc((uint32_t**)&prm->d_tables, total));
+  MICK_TRY(dev_alloc(prm->alloc, (uint32_t**)&prm->d_tables, total));
   uint32_t* d = (uint32_t*)prm->d_tables;
   MICK_HIP(hipMemcpy(d, h.data(), total * 4, hipMemcpyHostToDevice), "table upload");
   prm->dt.mod = d;
@@ -225,7 +221,7 @@ int build_tables(mick_params* prm) {
       mu.insert(mu.end(), C.begin(), C.end());
     }
   }
-  MICK_TRY(dev_alloc(&prm->d_modup, mu.size()));
+  MICK_TRY(dev_alloc(prm->alloc, &prm->d_modup, mu.size()));
   MICK_HIP(hipMemcpy(prm->d_modup, mu.data(), mu.size() * 4, hipMemcpyHostToDevice), "modup upload");
 
   // ---- per level: the inverse transform's N^-1 constants times qhat_j^-1
@@ -248,7 +244,7 @@ int build_tables(mick_params* prm) {
       ds.push_back(shoup_companion(f2, qj));
     }
   }
-  MICK_TRY(dev_alloc(&prm->d_dscale, ds.size()));
+  MICK_TRY(dev_alloc(prm->alloc, &prm->d_dscale, ds.size()));
   MICK_HIP(hipMemcpy(prm->d_dscale, ds.data(), ds.size() * 4, hipMemcpyHostToDevice), "dscale upload");
 
   // ---- ModDown tables and the chain constants q_d^-1 mod q_t
@@ -270,7 +266,7 @@ int build_tables(mick_params* prm) {
       md.push_back(shoup_companion(v, prm->q[t]));
     }
   }
-  MICK_TRY(dev_alloc(&prm->d_moddown, md.size()));
+  MICK_TRY(dev_alloc(prm->alloc, &prm->d_moddown, md.size()));
   MICK_HIP(hipMemcpy(prm->d_moddown, md.data(), md.size() * 4, hipMemcpyHostToDevice), "moddown upload");
 
   // ---- rescale constants g^{mu,t}_eta per (level, mu), eq. (g(u,t,eta))
@@ -294,7 +290,7 @@ int build_tables(mick_params* prm) {
       rs.insert(rs.end(), g.begin(), g.end());
     }
   }
-  MICK_TRY(dev_alloc(&prm->d_rescale, rs.size()));
+  MICK_TRY(dev_alloc(prm->alloc, &prm->d_rescale, rs.size()));
   if (!rs.empty()) MICK_HIP(hipMemcpy(prm->d_rescale, rs.data(), rs.size() * 4, hipMemcpyHostToDevice), "rs upload");
 
   // device copies of the table offsets, for the job-table kernels
@@ -303,7 +299,7 @@ int build_tables(mick_params* prm) {
     for (size_t v : prm->modup_off) off.push_back((uint32_t)v);
     for (size_t v : prm->rescale_off) off.push_back((uint32_t)v);
     for (size_t v : prm->dscale_off) off.push_back((uint32_t)v);
-    MICK_TRY(dev_alloc(&prm->d_offsets, off.size()));
+    MICK_TRY(dev_alloc(prm->alloc, &prm->d_offsets, off.size()));
     MICK_HIP(hipMemcpy(prm->d_offsets, off.data(), off.size() * 4, hipMemcpyHostToDevice), "offset upload");
   }
 
@@ -453,6 +449,7 @@ int mick_params_create(int log_n, int L, int K, int dnum, mick_params** out) {
   p->K = K;
   p->dnum = dnum;
   p->alpha = alpha;
+  p->alloc = current_allocator();
   p->q = ntt_primes(30, 2 * (uint64_t)p->N, L);
   p->p = ntt_primes(31, 2 * (uint64_t)p->N, K);
   if ((int)p->q.size() < L || (int)p->p.size() < K) return set_error(MICK_E_ARG, "not enough NTT-friendly primes");
@@ -471,15 +468,123 @@ int mick_params_create(int log_n, int L, int K, int dnum, mick_params** out) {
   return MICK_OK;
 }
 
+static void free_tables(mick_params* prm) {
+  for (void** p : {(void**)&prm->d_tables, (void**)&prm->d_modup, (void**)&prm->d_moddown, (void**)&prm->d_rescale,
+                   (void**)&prm->d_dscale, (void**)&prm->d_offsets}) {
+    dev_free(prm->alloc, *p);
+    *p = nullptr;
+  }
+}
+
 void mick_params_destroy(mick_params* prm) {
   if (!prm) return;
-  if (prm->d_tables) (void)hipFree(prm->d_tables);
-  if (prm->d_modup) (void)hipFree(prm->d_modup);
-  if (prm->d_moddown) (void)hipFree(prm->d_moddown);
-  if (prm->d_rescale) (void)hipFree(prm->d_rescale);
-  if (prm->d_dscale) (void)hipFree(prm->d_dscale);
-  if (prm->d_offsets) (void)hipFree(prm->d_offsets);
+  free_tables(prm);
   delete prm;
+}
+
+static bool schedule_ok(int log_n, int a) { return (a == 7 || a == 8) && log_n - a >= 6 && log_n - a <= 8; }
+
+int mick_params_set_schedule(mick_params* prm, int first_pass_log) {
+  if (!prm) return set_error(MICK_E_ARG, "NULL params");
+  if (!schedule_ok(prm->log_n, first_pass_log))
+    return set_error(MICK_E_ARG, "first pass must be 7 or 8 stages with 6..8 left for the second");
+  if (first_pass_log == prm->split_a) return MICK_OK;
+  MICK_HIP(hipDeviceSynchronize(), "schedule sync");
+  const int old = prm->split_a;
+  free_tables(prm);
+  prm->split_a = first_pass_log;
+  prm->split_b = prm->log_n - first_pass_log;
+  int st = build_tables(prm);
+  if (st != MICK_OK) {  // restore the previous schedule
+    free_tables(prm);
+    prm->split_a = old;
+    prm->split_b = prm->log_n - old;
+    (void)build_tables(prm);
+  }
+  return st;
+}
+
+int mick_params_schedule(const mick_params* prm) { return prm ? prm->split_a : set_error(MICK_E_ARG, "NULL params"); }
+
+int mick_autotune(mick_params* prm, const char* cache_path) {
+  if (!prm) return set_error(MICK_E_ARG, "NULL params");
+  std::vector<int> cand;
+  for (int a : {7, 8})
+    if (schedule_ok(prm->log_n, a)) cand.push_back(a);
+  if (cand.size() == 1) return mick_params_set_schedule(prm, cand[0]);
+  const char* path = cache_path ? cache_path : getenv("MICK_AUTOTUNE_CACHE");
+  hipDeviceProp_t prop;
+  MICK_HIP(hipGetDeviceProperties(&prop, prm->device), "device properties");
+  char key[256];
+  snprintf(key, sizeof key, "%s %d %d %d %d %d", prop.gcnArchName, prop.multiProcessorCount, prm->log_n, prm->L,
+           prm->K, prm->dnum);
+  for (char* c = key; *c; c++)
+    if (*c == ':') *c = '_';  // keep the arch name one token
+  if (path) {
+    if (FILE* f = fopen(path, "r")) {
+      char line[512];
+      int found = 0;
+      while (fgets(line, sizeof line, f)) {
+        char arch[128];
+        int cus, ln, l, k, d, a;
+        double us;
+        if (sscanf(line, "mick-schedule %127s %d %d %d %d %d %d %lf", arch, &cus, &ln, &l, &k, &d, &a, &us) != 8)
+          continue;
+        char k2[256];
+        snprintf(k2, sizeof k2, "%s %d %d %d %d %d", arch, cus, ln, l, k, d);
+        if (strcmp(k2, key) == 0 && schedule_ok(prm->log_n, a)) found = a;  // the last entry wins
+      }
+      fclose(f);
+      if (found) return mick_params_set_schedule(prm, found);
+    }
+  }
+  // time forward + inverse transforms of all L + K limbs under each schedule
+  const int E = prm->L + prm->K;
+  const size_t words = (size_t)E * prm->N;
+  uint32_t* buf = nullptr;
+  MICK_TRY(dev_alloc(prm->alloc, &buf, words));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = prm->split_a;
+  double best_us = 1e30;
+  int st = [&]() -> int {
+    MICK_HIP(hipMemset(buf, 0, words * 4), "autotune clear");
+    MICK_HIP(hipEventCreate(&e0), "event");
+    MICK_HIP(hipEventCreate(&e1), "event");
+    const LimbMap mp = simple_map(prm, 0, E);
+    constexpr int kReps = 10;
+    for (int a : cand) {
+      MICK_TRY(mick_params_set_schedule(prm, a));
+      MICK_TRY(ntt_launch(prm, buf, buf, mp, E, 1, false, nullptr));  // warm-up
+      MICK_TRY(ntt_launch(prm, buf, buf, mp, E, 1, true, nullptr));
+      MICK_HIP(hipEventRecord(e0, nullptr), "event");
+      for (int r = 0; r < kReps; r++) {
+        MICK_TRY(ntt_launch(prm, buf, buf, mp, E, 1, false, nullptr));
+        MICK_TRY(ntt_launch(prm, buf, buf, mp, E, 1, true, nullptr));
+      }
+      MICK_HIP(hipEventRecord(e1, nullptr), "event");
+      MICK_HIP(hipEventSynchronize(e1), "event");
+      float ms = 0;
+      MICK_HIP(hipEventElapsedTime(&ms, e0, e1), "event");
+      const double us = 1e3 * ms / kReps;
+      if (us < best_us) {
+        best_us = us;
+        best = a;
+      }
+    }
+    return MICK_OK;
+  }();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  dev_free(prm->alloc, buf);
+  MICK_TRY(st);
+  MICK_TRY(mick_params_set_schedule(prm, best));
+  if (path) {
+    if (FILE* f = fopen(path, "a")) {
+      fprintf(f, "mick-schedule %s %d %.2f\n", key, best, best_us);
+      fclose(f);
+    }
+  }
+  return MICK_OK;
 }
 
 int mick_params_moduli(const mick_params* prm, uint32_t* q_host, uint32_t* p_host) {
@@ -508,24 +613,31 @@ int mick_keygen(const mick_params* prm, uint64_t seed, int k_max, void* stream, 
   const size_t NE = (size_t)E * N;
   std::unique_ptr<mick_keys> keys(new mick_keys());
   keys->prm = prm;
+  keys->alloc = current_allocator();
   keys->k_max = k_max;
   keys->seed = seed;
   keys->s = sample_ternary(stream_key(seed, "SK"), N, kSecretWeight);
-  MICK_TRY(dev_alloc(&keys->d_S, NE));
-  MICK_TRY(dev_alloc(&keys->d_pk, 2 * (size_t)L * N));
-  MICK_TRY(dev_alloc(&keys->d_evk, (size_t)(k_max - 1) * prm->dnum * 2 * NE));
+  const int st_alloc = [&]() -> int {
+    MICK_TRY(dev_alloc(keys->alloc, &keys->d_S, NE));
+    MICK_TRY(dev_alloc(keys->alloc, &keys->d_pk, 2 * (size_t)L * N));
+    return dev_alloc(keys->alloc, &keys->d_evk, (size_t)(k_max - 1) * prm->dnum * 2 * NE);
+  }();
+  if (st_alloc != MICK_OK) {
+    mick_keys_destroy(keys.release());
+    return st_alloc;
+  }
   uint32_t *tE = nullptr, *tA = nullptr, *tSt = nullptr, *tRow = nullptr;
   auto cleanup = [&]() {
-    if (tE) (void)hipFree(tE);
-    if (tA) (void)hipFree(tA);
-    if (tSt) (void)hipFree(tSt);
-    if (tRow) (void)hipFree(tRow);
+    dev_free(keys->alloc, tE);
+    dev_free(keys->alloc, tA);
+    dev_free(keys->alloc, tSt);
+    dev_free(keys->alloc, tRow);
   };
   int st = [&]() -> int {
-    MICK_TRY(dev_alloc(&tE, NE));
-    MICK_TRY(dev_alloc(&tA, NE));
-    MICK_TRY(dev_alloc(&tSt, NE));
-    MICK_TRY(dev_alloc(&tRow, (size_t)E * 4));
+    MICK_TRY(dev_alloc(keys->alloc, &tE, NE));
+    MICK_TRY(dev_alloc(keys->alloc, &tA, NE));
+    MICK_TRY(dev_alloc(keys->alloc, &tSt, NE));
+    MICK_TRY(dev_alloc(keys->alloc, &tRow, (size_t)E * 4));
     const GaussTable gt = gauss_table(kSigma);
     // S = NTT(s) over every modulus
     MICK_TRY(upload(keys->d_S, residues(prm, keys->s.data(), 0, E), s));
@@ -584,9 +696,9 @@ int mick_keygen(const mick_params* prm, uint64_t seed, int k_max, void* stream, 
 
 void mick_keys_destroy(mick_keys* keys) {
   if (!keys) return;
-  if (keys->d_S) (void)hipFree(keys->d_S);
-  if (keys->d_pk) (void)hipFree(keys->d_pk);
-  if (keys->d_evk) (void)hipFree(keys->d_evk);
+  dev_free(keys->alloc, keys->d_S);
+  dev_free(keys->alloc, keys->d_pk);
+  dev_free(keys->alloc, keys->d_evk);
   delete keys;
 }
 
@@ -659,7 +771,7 @@ int mick_encrypt(const mick_params* prm, const mick_keys* keys, const int64_t* m
     hm[i] = (uint32_t)(((uint64_t)hm[i] + he0[i]) % m);
   }
   uint32_t* tmp = nullptr;
-  MICK_TRY(dev_alloc(&tmp, 3 * LN));
+  MICK_TRY(dev_alloc(prm->alloc, &tmp, 3 * LN));
   int st = [&]() -> int {
     MICK_TRY(upload(tmp, residues(prm, v.data(), 0, level), s));
     MICK_TRY(upload(tmp + LN, hm, s));
@@ -670,7 +782,7 @@ int mick_encrypt(const mick_params* prm, const mick_keys* keys, const int64_t* m
     MICK_HIP(hipStreamSynchronize(s), "encrypt sync");
     return MICK_OK;
   }();
-  (void)hipFree(tmp);
+  dev_free(prm->alloc, tmp);
   return st;
 }
 
@@ -678,7 +790,7 @@ static int decrypt_res(const mick_params* prm, const mick_keys* keys, const uint
                        uint32_t* res_host, hipStream_t s) {
   const size_t LN = (size_t)level * prm->N;
   uint32_t* tmp = nullptr;
-  MICK_TRY(dev_alloc(&tmp, LN));
+  MICK_TRY(dev_alloc(prm->alloc, &tmp, LN));
   int st = [&]() -> int {
     MICK_TRY(launch_dec(prm, ct_dev, keys->d_S, tmp, level, s));
     MICK_TRY(ntt_launch(prm, tmp, tmp, simple_map(prm, 0, level), level, 1, true, s));
@@ -686,7 +798,7 @@ static int decrypt_res(const mick_params* prm, const mick_keys* keys, const uint
     MICK_HIP(hipStreamSynchronize(s), "decrypt sync");
     return MICK_OK;
   }();
-  (void)hipFree(tmp);
+  dev_free(prm->alloc, tmp);
   return st;
 }
 
@@ -895,26 +1007,53 @@ GroupConsts group_consts(const mick_params* prm, const mick_keys* keys) {
 
 }  // namespace
 
-extern "C" {
+namespace mick {
 
-size_t mick_jobs_workspace_bytes(const mick_params* prm, const mick_job* jobs, int n_jobs) {
-  if (!prm || !jobs || n_jobs < 1) return 0;
-  size_t total = align_up((size_t)n_jobs * sizeof(JobDesc));
-  for (int i = 0; i < n_jobs; i++) {
-    const int k = jobs[i].k, level = jobs[i].level;
-    if (k < 2 || k > kMaxK || level < k || level > prm->L) return 0;
-    total += align_up(WsLayout(k, level, prm->K, prm->alpha, prm->log_n).total * 4);
-  }
-  return total;
+namespace {
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+}  // namespace
+
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
 }
 
-int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs, void* ws,
-                   size_t ws_bytes, void* stream, mick_plan** out) {
-  if (!out) return set_error(MICK_E_ARG, "NULL out");
-  *out = nullptr;
-  if (!prm || !keys || !jobs || !ws) return set_error(MICK_E_ARG, "NULL argument");
-  if (keys->prm != prm) return set_error(MICK_E_ARG, "keys belong to other params");
-  if (n_jobs < 1 || n_jobs > 65536) return set_error(MICK_E_ARG, "n_jobs must be in 1..65536");
+int dev_alloc_bytes(const Allocator& a, void** p, size_t bytes) {
+  *p = nullptr;
+  if (a.alloc) {
+    *p = a.alloc(bytes, a.ctx);
+    if (!*p) return set_error(MICK_E_NOMEM, "registered allocator returned NULL");
+    if (((uintptr_t)*p & 255) != 0) {
+      a.release(*p, a.ctx);
+      *p = nullptr;
+      return set_error(MICK_E_NOMEM, "registered allocator returned a pointer not aligned to 256 bytes");
+    }
+    return MICK_OK;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return set_error(MICK_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return MICK_OK;
+}
+
+void dev_free(const Allocator& a, void* p) {
+  if (!p) return;
+  if (a.release)
+    a.release(p, a.ctx);
+  else
+    (void)hipFree(p);
+}
+
+size_t job_ws_bytes(const mick_params* prm, int k, int level) {
+  return align_up(WsLayout(k, level, prm->K, prm->alpha, prm->log_n).total * 4);
+}
+
+size_t table_bytes(int n_jobs) { return align_up((size_t)n_jobs * sizeof(JobDesc)); }
+
+int check_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs) {
   for (int i = 0; i < n_jobs; i++) {
     const mick_job& jb = jobs[i];
     MICK_TRY(check_mul(prm, keys, jb.k, jb.level));
@@ -922,21 +1061,23 @@ int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job
     for (int u = 0; u < jb.k; u++)
       if (!jb.cts[u]) return set_error(MICK_E_ARG, "NULL ciphertext pointer");
   }
-  if (ws_bytes < mick_jobs_workspace_bytes(prm, jobs, n_jobs)) return set_error(MICK_E_WS, "workspace too small");
-  hipStream_t s = (hipStream_t)stream;
+  return MICK_OK;
+}
+
+int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs,
+              uint32_t* const* job_ws, JobDesc* table_dev, std::vector<JobDesc>& jt, hipStream_t s,
+              mick_plan** out) {
   std::unique_ptr<mick_plan> plan(new mick_plan());
   plan->prm = prm;
   plan->keys = keys;
-  plan->table = (JobDesc*)ws;
+  plan->table = table_dev;
   plan->n_jobs = n_jobs;
   // jobs of equal k are contiguous in the table (the tensor and rescale kernels
   // are specialised on k)
   std::vector<int> order(n_jobs);
   for (int i = 0; i < n_jobs; i++) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobs[a].k < jobs[b].k; });
-  std::vector<JobDesc> jt(n_jobs);
-  char* base = (char*)ws;
-  size_t off = align_up((size_t)n_jobs * sizeof(JobDesc));
+  jt.assign(n_jobs, JobDesc{});
   int total[kStages] = {0};
   for (int r = 0; r < n_jobs; r++) {
     const mick_job& jb = jobs[order[r]];
@@ -944,10 +1085,9 @@ int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job
     memset(&d, 0, sizeof(d));
     for (int u = 0; u < jb.k; u++) d.in[u] = jb.cts[u];
     d.out = jb.out;
-    d.ws = (uint32_t*)(base + off);
+    d.ws = job_ws[order[r]];
     d.k = jb.k;
     d.level = jb.level;
-    off += align_up(WsLayout(jb.k, jb.level, prm->K, prm->alpha, prm->log_n).total * 4);
     int nb[kStages];
     job_blocks(prm, jb.k, jb.level, nb);
     for (int st = 0; st < kStages; st++) {
@@ -967,9 +1107,54 @@ int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job
     run.moddown_blocks = total[S_MODDOWN];
   }
   for (int st = 0; st < kStages; st++) plan->blocks[st] = total[st];
-  MICK_HIP(hipMemcpyAsync(plan->table, jt.data(), n_jobs * sizeof(JobDesc), hipMemcpyHostToDevice, s), "job table");
+  MICK_HIP(hipMemcpyAsync(table_dev, jt.data(), n_jobs * sizeof(JobDesc), hipMemcpyHostToDevice, s), "job table");
   *out = plan.release();
   return MICK_OK;
+}
+
+}  // namespace mick
+
+extern "C" {
+
+int mick_set_allocator(mick_alloc_fn alloc, mick_free_fn release, void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr)) return set_error(MICK_E_ARG, "give both functions or neither");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.release = release;
+  g_alloc.ctx = alloc ? ctx : nullptr;
+  return MICK_OK;
+}
+
+size_t mick_jobs_workspace_bytes(const mick_params* prm, const mick_job* jobs, int n_jobs) {
+  if (!prm || !jobs || n_jobs < 1) return 0;
+  size_t total = table_bytes(n_jobs);
+  for (int i = 0; i < n_jobs; i++) {
+    const int k = jobs[i].k, level = jobs[i].level;
+    if (k < 2 || k > kMaxK || level < k || level > prm->L) return 0;
+    total += job_ws_bytes(prm, k, level);
+  }
+  return total;
+}
+
+int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs, void* ws,
+                   size_t ws_bytes, void* stream, mick_plan** out) {
+  if (!out) return set_error(MICK_E_ARG, "NULL out");
+  *out = nullptr;
+  if (!prm || !keys || !jobs || !ws) return set_error(MICK_E_ARG, "NULL argument");
+  if (keys->prm != prm) return set_error(MICK_E_ARG, "keys belong to other params");
+  if (n_jobs < 1 || n_jobs > 65536) return set_error(MICK_E_ARG, "n_jobs must be in 1..65536");
+  MICK_TRY(check_jobs(prm, keys, jobs, n_jobs));
+  if (ws_bytes < mick_jobs_workspace_bytes(prm, jobs, n_jobs)) return set_error(MICK_E_WS, "workspace too small");
+  // table first, then the jobs' workspaces back to back
+  std::vector<uint32_t*> job_ws(n_jobs);
+  char* base = (char*)ws;
+  size_t off = align_up((size_t)n_jobs * sizeof(JobDesc));
+  for (int i = 0; i < n_jobs; i++) {
+    job_ws[i] = (uint32_t*)(base + off);
+    off += job_ws_bytes(prm, jobs[i].k, jobs[i].level);
+  }
+  std::vector<JobDesc> host_table;
+  return plan_jobs(prm, keys, jobs, n_jobs, job_ws.data(), (JobDesc*)ws, host_table, (hipStream_t)stream, out);
 }
 
 int mick_plan_execute(const mick_plan* plan, void* stream) {

@@ -101,8 +101,25 @@ struct mick_params_impl;
 
 }  // namespace mick
 
+namespace mick {
+
+// Device allocator of long-lived objects (mick_set_allocator); null
+// functions mean hipMalloc / hipFree.  Each object keeps the allocator that
+// created it and frees its memory with the same one.
+struct Allocator {
+  mick_alloc_fn alloc = nullptr;
+  mick_free_fn release = nullptr;
+  void* ctx = nullptr;
+};
+Allocator current_allocator();
+int dev_alloc_bytes(const Allocator& a, void** p, size_t bytes);
+void dev_free(const Allocator& a, void* p);
+
+}  // namespace mick
+
 struct mick_params {
   int log_n, N, L, K, dnum, alpha;
+  mick::Allocator alloc;
   std::vector<uint32_t> q, p, mods;  // mods = q ++ p
   int device;
   // device allocations
@@ -145,6 +162,7 @@ struct mick_plan {
 
 struct mick_keys {
   const mick_params* prm;
+  mick::Allocator alloc;
   int k_max;
   uint64_t seed;
   std::vector<int64_t> s;  // host copy of the secret
@@ -190,6 +208,13 @@ struct ProfScope {
 int set_error(int status, const std::string& msg);
 int hip_error(hipError_t e, const char* what);
 
+#define MICK_TRY(expr)              \
+  do {                              \
+    int _st = (expr);               \
+    if (_st != MICK_OK) return _st; \
+  } while (0)
+#define MICK_HIP(expr, what) MICK_TRY(::mick::hip_error((expr), (what)))
+
 // Transforms (ntt.hip).  src may equal dst.
 int ntt_launch(const mick_params* prm, const uint32_t* src, uint32_t* dst, const LimbMap& map, int n_limbs, int n_jobs,
                bool inverse, hipStream_t s, int site = P_OTHER);
@@ -201,5 +226,17 @@ inline size_t evk_offset(const mick_params* prm, int t, int b, int l) {
 }
 
 inline int digits_at(const mick_params* prm, int level) { return (level + prm->alpha - 1) / prm->alpha; }
+
+// Job tables (api.hip).  job_ws_bytes: one job's workspace (aligned);
+// table_bytes: a table of n_jobs entries (aligned).  check_jobs validates
+// shapes, keys and pointers.  plan_jobs writes the table of n_jobs jobs
+// (job i using the workspace job_ws[i]) to table_dev with an asynchronous
+// copy from jt, which the caller keeps alive until the copy has run.
+size_t job_ws_bytes(const mick_params* prm, int k, int level);
+size_t table_bytes(int n_jobs);
+int check_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs);
+int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs,
+              uint32_t* const* job_ws, JobDesc* table_dev, std::vector<JobDesc>& jt, hipStream_t s,
+              mick_plan** out);
 
 }  // namespace mick

@@ -57,6 +57,20 @@ _SIGS = {
                                       ctypes.POINTER(_vp)]),
     "mick_plan_execute": (ctypes.c_int, [_vp, _vp]),
     "mick_plan_destroy": (None, [_vp]),
+    "mick_queue_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_size_t,
+                                         ctypes.POINTER(_vp)]),
+    "mick_queue_job_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "mick_queue_push": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "mick_queue_run": (ctypes.c_int, [_vp, _vp]),
+    "mick_queue_poll": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]),
+    "mick_queue_drain": (ctypes.c_int, [_vp, _vp]),
+    "mick_queue_info": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "mick_queue_destroy": (None, [_vp]),
+    "mick_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "mick_params_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "mick_params_schedule": (ctypes.c_int, [_vp]),
+    "mick_set_allocator": (ctypes.c_int, [_vp, _vp, _vp]),
     "mick_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "mick_profile_collect": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
@@ -69,6 +83,12 @@ class Job(ctypes.Structure):
     """mick_job: one multiply of a heterogeneous batch."""
     _fields_ = [("k", ctypes.c_int), ("level", ctypes.c_int), ("cts", ctypes.c_void_p * 12),
                 ("out", ctypes.c_void_p)]
+
+
+class QJob(ctypes.Structure):
+    """mick_qjob: one multiply pushed to a queue."""
+    _fields_ = [("id", ctypes.c_uint64), ("set", ctypes.c_int), ("k", ctypes.c_int), ("level", ctypes.c_int),
+                ("cts", ctypes.c_void_p * 12), ("out", ctypes.c_void_p)]
 
 
 class MickError(RuntimeError):
@@ -385,3 +405,123 @@ def profile_collect():
     if n < 0:
         raise MickError(n, "mick_profile_collect")
     return {names[i].decode(): (ms[i], cnt[i]) for i in range(n)}
+
+
+# ---------------------------------------------------------------- queue
+
+class Queue:
+    """mick_queue over several parameter sets (with their keys) and a device
+    workspace arena of `capacity` bytes.  push() keeps the input and output
+    tensors of each job alive until poll() or drain() reports it done."""
+
+    def __init__(self, sets: Sequence[tuple], capacity: int):
+        self.sets = list(sets)  # [(Params, Keys)], kept alive
+        n = len(self.sets)
+        prms = (_vp * n)(*[p.handle.value for p, _ in self.sets])
+        keys = (_vp * n)(*[k.handle.value for _, k in self.sets])
+        h = _vp()
+        _check(load().mick_queue_create(prms, keys, n, capacity, ctypes.byref(h)), "mick_queue_create")
+        self._h = h
+        self._live = {}  # id -> tensors of the job
+
+    def job_bytes(self, set_index: int, k: int, level: int) -> int:
+        return load().mick_queue_job_bytes(self._h, set_index, k, level)
+
+    def push(self, jobs):
+        """jobs: iterable of (id, set_index, cts, level, out) with cts k tensors
+        [2, level, N] and out a [2, level - k + 1, N] tensor."""
+        jobs = list(jobs)
+        arr = (QJob * len(jobs))()
+        for i, (jid, st, cts, level, out) in enumerate(jobs):
+            arr[i].id, arr[i].set, arr[i].k, arr[i].level = jid, st, len(cts), level
+            for u, c in enumerate(cts):
+                arr[i].cts[u] = _ptr(c).value
+            arr[i].out = _ptr(out).value
+        _check(load().mick_queue_push(self._h, ctypes.cast(arr, _vp), len(jobs)), "mick_queue_push")
+        for jid, _st, cts, _lv, out in jobs:
+            self._live[jid] = (cts, out)
+
+    def run(self) -> int:
+        n = load().mick_queue_run(self._h, _stream())
+        if n < 0:
+            raise MickError(n, "mick_queue_run")
+        return n
+
+    def poll(self, max_ids: int = 4096):
+        buf = (ctypes.c_uint64 * max_ids)()
+        n = load().mick_queue_poll(self._h, buf, max_ids)
+        if n < 0:
+            raise MickError(n, "mick_queue_poll")
+        ids = [buf[i] for i in range(n)]
+        for i in ids:
+            self._live.pop(i, None)
+        return ids
+
+    def drain(self):
+        _check(load().mick_queue_drain(self._h, _stream()), "mick_queue_drain")
+        self._live.clear()
+
+    def info(self):
+        p, r, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        _check(load().mick_queue_info(self._h, ctypes.byref(p), ctypes.byref(r), ctypes.byref(b)), "mick_queue_info")
+        return p.value, r.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mick_queue_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        self.close()
+
+
+# ---------------------------------------------------------------- schedule, allocator
+
+def autotune(prm: Params, cache_path: str | None = None) -> int:
+    """Chooses the transform schedule of `prm` by timing (or from the cache
+    file); returns the first-pass log size now in use."""
+    _check(load().mick_autotune(prm.handle, cache_path.encode() if cache_path else None), "mick_autotune")
+    return schedule(prm)
+
+
+def set_schedule(prm: Params, first_pass_log: int):
+    _check(load().mick_params_set_schedule(prm.handle, first_pass_log), "mick_params_set_schedule")
+
+
+def schedule(prm: Params) -> int:
+    v = load().mick_params_schedule(prm.handle)
+    if v < 0:
+        raise MickError(v, "mick_params_schedule")
+    return v
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None  # keeps the registered callbacks alive
+
+
+def use_torch_allocator(on: bool = True):
+    """Routes the library's own device allocations (tables, keys, queue
+    arenas) through PyTorch's caching allocator (on=True) or back to
+    hipMalloc (on=False).  Objects keep the allocator they were created
+    with."""
+    global _allocator_refs
+    if not on:
+        _check(load().mick_set_allocator(None, None, None), "mick_set_allocator")
+        return
+
+    def _alloc(nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(max(int(nbytes), 1))
+        except Exception:  # out of memory: the library reports MICK_E_NOMEM
+            return None
+
+    def _free(ptr, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    refs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(load().mick_set_allocator(ctypes.cast(refs[0], _vp), ctypes.cast(refs[1], _vp), None),
+           "mick_set_allocator")
+    # earlier callbacks stay referenced: objects created with them still free through them
+    _allocator_refs = (refs, _allocator_refs)

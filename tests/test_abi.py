@@ -39,3 +39,43 @@ def test_status_strings_without_gpu():
     assert lib.mick_params_create(12, 3, 1, 3, ctypes.byref(out)) == -1
     assert lib.mick_params_create(13, 3, 9, 3, ctypes.byref(out)) == -1
     assert lib.mick_params_create(16, 32, 8, 2, ctypes.byref(out)) == -1
+
+
+def test_queue_schedule_allocator_validate_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    out = vp()
+    # queue: NULL arrays, bad set counts, tiny capacity
+    lib.mick_queue_create.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)]
+    assert lib.mick_queue_create(None, None, 1, 1 << 20, ctypes.byref(out)) == -1
+    arr = (vp * 1)(None)
+    assert lib.mick_queue_create(ctypes.cast(arr, vp), ctypes.cast(arr, vp), 0, 1 << 20, ctypes.byref(out)) == -1
+    assert lib.mick_queue_create(ctypes.cast(arr, vp), ctypes.cast(arr, vp), 17, 1 << 20, ctypes.byref(out)) == -1
+    assert lib.mick_queue_create(ctypes.cast(arr, vp), ctypes.cast(arr, vp), 1, 64, ctypes.byref(out)) == -1
+    assert lib.mick_queue_create(ctypes.cast(arr, vp), ctypes.cast(arr, vp), 1, 1 << 20, ctypes.byref(out)) == -1
+    assert out.value is None
+    lib.mick_queue_push.argtypes = [vp, vp, ctypes.c_int]
+    assert lib.mick_queue_push(None, None, 1) == -1
+    lib.mick_queue_run.argtypes = [vp, vp]
+    assert lib.mick_queue_run(None, None) == -1
+    lib.mick_queue_drain.argtypes = [vp, vp]
+    assert lib.mick_queue_drain(None, None) == -1
+    lib.mick_queue_info.argtypes = [vp, vp, vp, vp]
+    assert lib.mick_queue_info(None, None, None, None) == -1
+    lib.mick_queue_job_bytes.restype = ctypes.c_size_t
+    lib.mick_queue_job_bytes.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    assert lib.mick_queue_job_bytes(None, 0, 2, 3) == 0
+    lib.mick_queue_destroy.argtypes = [vp]
+    lib.mick_queue_destroy(None)  # NULL-safe
+    # schedule
+    lib.mick_params_schedule.argtypes = [vp]
+    assert lib.mick_params_schedule(None) == -1
+    lib.mick_params_set_schedule.argtypes = [vp, ctypes.c_int]
+    assert lib.mick_params_set_schedule(None, 8) == -1
+    lib.mick_autotune.argtypes = [vp, ctypes.c_char_p]
+    assert lib.mick_autotune(None, None) == -1
+    # allocator: both functions or neither
+    lib.mick_set_allocator.argtypes = [vp, vp, vp]
+    cb = ctypes.CFUNCTYPE(vp, ctypes.c_size_t, vp)(lambda n, c: None)
+    assert lib.mick_set_allocator(ctypes.cast(cb, vp), None, None) == -1
+    assert lib.mick_set_allocator(None, None, None) == 0
