@@ -123,20 +123,31 @@ def roofline(prof, steps, N, k, level, K, alpha, jobs):
             "algorithmic_bytes_per_launch": b}
 
 
+def kernel_source_hash():
+    """First 16 hex digits of a SHA-256 over the kernel sources (csrc/*.hip,
+    csrc/*.h in name order), recorded with the counter summaries."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2601_15401_amd", "csrc", "*.hip")) +
+                    glob.glob(os.path.join(ROOT, "paper_2601_15401_amd", "csrc", "*.h"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the transform source has changed since the counters
-    were taken (the summary records a hash of it)."""
-    import hashlib
+    summary, or None when the kernel sources have changed since the counters
+    were taken (the summary records their hash)."""
     path = os.path.join(ROOT, "profiles", "hbm_counters_n16_k8_b8.txt")
-    src = os.path.join(ROOT, "paper_2601_15401_amd", "csrc", "ntt.hip")
-    if not (os.path.exists(path) and os.path.exists(src)):
+    if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = kernel_source_hash()
     for line in open(path):
         if line.startswith("TRAFFIC "):
             f = dict(kv.split("=", 1) for kv in line.split()[1:])
-            if f.get("kernel") == kernel and f.get("ntt_sha256_16") == sha:
+            if f.get("kernel") == kernel and f.get("src_sha256_16") == sha:
                 return int(f["bytes"])
     return None
 
@@ -202,7 +213,10 @@ def run_mixed(args, torch, mick):
     for ln, (L, K, dnum) in MIXED_PARAMS.items():
         log("params N=2^%d L=%d K=%d dnum=%d; keygen k_max=%d ..." % (ln, L, K, dnum, min(12, L)))
         prms[ln] = mick.Params(ln, L, K, dnum)
+        mick.autotune(prms[ln])
         keys[ln] = mick.Keys(prms[ln], 40 + ln, min(12, L))
+    schedules = {str(ln): mick.schedule(prms[ln]) for ln in prms}
+    log("transform schedules (first-pass log size): %s" % schedules)
     log("inputs (uniform residues per limb) ...")
     for ln, k, level in spec:
         if (ln, level) not in pools:
@@ -279,6 +293,32 @@ def run_mixed(args, torch, mick):
         for ln in specs:  # the two forms agree
             for o, b in zip(outs[ln], plans[ln].outs):
                 assert torch.equal(o, b)
+    # the same 512 jobs through the native work queue (host admission, one
+    # plan per ring degree per run, event completion), wall clock incl. host
+    order = sorted(prms)
+    qsets = [(prms[ln], keys[ln]) for ln in order]
+    qjobs, qi = [], 0
+    for ln in order:
+        for c, lv, _ in specs.get(ln, []):
+            qjobs.append((qi, order.index(ln), c, lv,
+                          torch.empty(2, lv - len(c) + 1, 1 << ln, dtype=torch.int32, device="cuda")))
+            qi += 1
+    qu = mick.Queue(qsets, capacity=1 << 36)
+    qu.push(qjobs)
+    qu.drain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        qu.push(qjobs)
+        qu.drain()
+    torch.cuda.synchronize()
+    q_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    log("queue: %.3f ms per 512 multiplies (wall), %.1f ct-mults/s" % (q_ms, n_jobs / (q_ms / 1e3)))
+    for ln in order:  # the queue's outputs equal the graph's
+        outs_q = [j[4] for j in qjobs if j[1] == order.index(ln)]
+        for o, b in zip(outs_q, plans[ln].outs):
+            assert torch.equal(o, b)
+    qu.close()
     total_bytes = sum(job_bytes(1 << ln, k, lv, MIXED_PARAMS[ln][1], prms[ln].alpha) for ln, k, lv in spec)
     rec = {
         "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
@@ -290,6 +330,8 @@ def run_mixed(args, torch, mick):
                    "parallelism": "none"},
         "plain": plain,
         "batched_over_plain": round(value / plain["value"], 3) if plain else None,
+        "queue": {"value": round(n_jobs / (q_ms / 1e3), 2), "unit": "ct-mults/s", "ms_per_512_wall": round(q_ms, 3)},
+        "schedules": schedules,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4), "of": "one batch of 512"},
         "hbm_frac_whole_path": round(total_bytes / (step_ms.mean() / 1e3) / 1e9 / HBM_PEAK_GBS, 5),
@@ -314,6 +356,7 @@ def run_serve(args, torch, mick):
     for ln, (L, K, dnum) in MIXED_PARAMS.items():
         log("params N=2^%d L=%d K=%d dnum=%d; keygen k_max=%d ..." % (ln, L, K, dnum, min(12, L)))
         prms[ln] = mick.Params(ln, L, K, dnum)
+        mick.autotune(prms[ln])
         keys[ln] = mick.Keys(prms[ln], 50 + ln, min(12, L))
     log("input state: 12 ciphertexts per (N, level) in use ...")
     gen = torch.Generator(device="cuda")
