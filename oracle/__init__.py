@@ -20,5 +20,7 @@ keys     secret key, public key, evaluation keys for s^2..s^k (Sec. II, Sec. V-A
 ckks     encode / encrypt / decrypt / decode (Sec. II)
 mult     tensor product, ModUp, key inner product, ModDown (textbook and
          relocated), single and multi-level rescaling (Sec. II-V)
+tree     tree-structured n-input multiply with rescaling inside the tree and
+         its partition planner (Sec. V-B, V-C, Table II)
 counts   transform counters used to check the paper's operation counts
 """
