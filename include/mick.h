@@ -226,6 +226,40 @@ int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job
 int mick_plan_execute(const mick_plan* plan, void* stream);
 void mick_plan_destroy(mick_plan* plan);
 
+/* ---------------------------------------------------------------- tree multiply
+ * Sec. V-C: the n inputs are partitioned into groups, recursively.  A node
+ * multiplies the results of its children as polynomials in s (a group of g
+ * inputs is the product of g ciphertexts, eq. (d_u formula for n-ct mult));
+ * every node but the root then rescales each polynomial of its product by
+ * (fan-in - 1) levels with Algorithm 1 (Sec. V-B) in the NTT domain; the
+ * root relinearises its degree-n product with the keys for s^2..s^n and
+ * applies the relocated ModDown and (fan-in - 1)-level rescale of Sec. IV and
+ * eq. (multi rs).  The multiplicative depth is that of the tree (the flat
+ * multiply is the single group n, depth n - 1).
+ *
+ * A tree is an array of prefix tokens: g > 0 is a group of g consecutive
+ * inputs, -m (m >= 2) an internal node whose m subtrees follow.  Table II's
+ * "(4,3)|(2,2)" is {-2, -2, 2, 2, 3}.  Every subtree is evaluated at the
+ * level at which its result enters its parent: its inputs first drop their
+ * top limbs (the placement Table II's (I)NTT counts imply).
+ *
+ * mick_tree_plan writes the partition of n inputs (2..32) with the fewest
+ * rescale units (one per polynomial rescaled before relinearisation) at
+ * depth ceil(log2 n) (Sec. V-C, Table II); returns the number of tokens.
+ * mick_tree_shape validates a tree and reports its inputs, depth and units
+ * (any output pointer may be NULL).
+ * mick_mul_tree multiplies n = 2..12 ciphertexts cts_host[u] (device
+ * uint32[2][level][N], NTT domain) with keys up to s^n; the output is
+ * device uint32[2][level - depth][N], NTT domain; its scale is Delta^n over
+ * the product of every prime dropped by the tree's rescales (the caller
+ * tracks scales).  ws: at least mick_tree_workspace_bytes() bytes (0 for an
+ * invalid tree or level). */
+int mick_tree_plan(int n, int* tokens, int max_tokens);
+int mick_tree_shape(const int* tokens, int n_tokens, int* n_inputs, int* depth, int* rs_units);
+size_t mick_tree_workspace_bytes(const mick_params* prm, const int* tokens, int n_tokens, int level);
+int mick_mul_tree(const mick_params* prm, const mick_keys* keys, const uint32_t* const* cts_host, int level,
+                  const int* tokens, int n_tokens, uint32_t* ct_out_dev, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- work queue
  * A host-driven queue of multiplies over one or more parameter sets (for
  * instance the four ring degrees of a mixed workload), with admission by

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmick.so")
-HIP_SOURCES = ["ntt.hip", "rns.hip", "api.hip", "queue.hip"]
+HIP_SOURCES = ["ntt.hip", "rns.hip", "api.hip", "queue.hip", "tree.hip"]
 HOST_SOURCES = ["host_math.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are kept out of every kernel.

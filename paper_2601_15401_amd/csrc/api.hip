@@ -413,6 +413,17 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
 
 }  // namespace
 
+namespace mick {
+
+size_t mul_ws_words(const mick_params* prm, int k, int level) { return mul_layout(prm, k, level).total; }
+
+int relin_rescale_one(const mick_params* prm, const mick_keys* keys, int k, int level, int mu, uint32_t* ws,
+                      uint32_t* out, hipStream_t s) {
+  return relin_rescale_ws(prm, keys, k, level, mu, ws, mul_layout(prm, k, level).total, 1, out, 0, s);
+}
+
+}  // namespace mick
+
 // ====================================================================== C ABI
 
 extern "C" {
@@ -871,28 +882,41 @@ int mick_relin_k(const mick_params* prm, const mick_keys* keys, const uint32_t* 
   return relin_rescale_ws(prm, keys, k, level, 0, w, lay.total, 1, ct_out_dev, 0, s);
 }
 
+}  // extern "C"
+
+namespace mick {
+
+// Algorithm 1 on `polys` NTT-domain polynomials in[polys][level][N] ->
+// out[polys][level-mu][N]; ws holds polys level N words.
+int rescale_polys(const mick_params* prm, const uint32_t* in, int polys, int level, int mu, uint32_t* out,
+                  uint32_t* ws, hipStream_t s) {
+  const size_t N = prm->N;
+  const int top = level - mu;
+  uint32_t* topc = ws;
+  uint32_t* bb = topc + (size_t)polys * mu * N;
+  // step 1: INTT of the mu dropped limbs of every polynomial
+  MICK_HIP(hipMemcpy2DAsync(topc, (size_t)mu * N * 4, in + (size_t)top * N, (size_t)level * N * 4,
+                            (size_t)mu * N * 4, polys, hipMemcpyDeviceToDevice, s),
+           "stage dropped limbs");
+  MICK_TRY(ntt_launch(prm, topc, topc, simple_map(prm, top, mu), polys * mu, 1, true, s));
+  // steps 2 and 3: chain, sums, NTT, combine
+  MdArgs A = md_args(prm, level, mu);
+  MICK_TRY(launch_rs_sums(prm, topc, bb, A, mu, polys, s));
+  MICK_TRY(ntt_launch(prm, bb, bb, simple_map(prm, 0, top), polys * top, 1, false, s));
+  return launch_rs_combine(prm, in, bb, out, A, mu, polys, s);
+}
+
+}  // namespace mick
+
+extern "C" {
+
 int mick_rescale_multi(const mick_params* prm, const uint32_t* ct_in_dev, int level, int mu, uint32_t* ct_out_dev,
                        void* ws, size_t ws_bytes, void* stream) {
   if (!prm || !ct_in_dev || !ct_out_dev || !ws) return set_error(MICK_E_ARG, "NULL argument");
   if (level < 2 || level > prm->L || mu < 1 || mu >= level) return set_error(MICK_E_LEVEL, "need 1 <= mu < level <= L");
   if (mu > 16) return set_error(MICK_E_ARG, "mu must be at most 16");
   if (ws_bytes < mick_workspace_bytes(prm, MICK_OP_RESCALE, mu, level)) return set_error(MICK_E_WS, "workspace too small");
-  hipStream_t s = (hipStream_t)stream;
-  const size_t N = prm->N;
-  const int top = level - mu;
-  uint32_t* topc = (uint32_t*)ws;
-  uint32_t* bb = topc + 2 * (size_t)mu * N;
-  // Algorithm 1 step 1: INTT of the mu dropped limbs
-  MICK_HIP(hipMemcpy2DAsync(topc, (size_t)mu * N * 4, ct_in_dev + (size_t)top * N, (size_t)level * N * 4,
-                            (size_t)mu * N * 4, 2, hipMemcpyDeviceToDevice, s),
-           "stage dropped limbs");
-  LimbMap mt = simple_map(prm, top, mu);
-  MICK_TRY(ntt_launch(prm, topc, topc, mt, 2 * mu, 1, true, s));
-  // steps 2 and 3: chain, sums, NTT, combine
-  MdArgs A = md_args(prm, level, mu);
-  MICK_TRY(launch_rs_sums(prm, topc, bb, A, mu, s));
-  MICK_TRY(ntt_launch(prm, bb, bb, simple_map(prm, 0, top), 2 * top, 1, false, s));
-  return launch_rs_combine(prm, ct_in_dev, bb, ct_out_dev, A, mu, s);
+  return rescale_polys(prm, ct_in_dev, 2, level, mu, ct_out_dev, (uint32_t*)ws, (hipStream_t)stream);
 }
 
 int mick_mul_relin_rescale(const mick_params* prm, const mick_keys* keys, const uint32_t* const* cts_host, int k,

@@ -232,6 +232,13 @@ inline int digits_at(const mick_params* prm, int level) { return (level + prm->a
 // shapes, keys and pointers.  plan_jobs writes the table of n_jobs jobs
 // (job i using the workspace job_ws[i]) to table_dev with an asynchronous
 // copy from jt, which the caller keeps alive until the copy has run.
+// One multiply's workspace in words (D, scaled d_t, ModUp outputs,
+// accumulators) and the relinearisation of the degree-k product D at the
+// start of `ws` followed by mu rescales (api.hip).
+size_t mul_ws_words(const mick_params* prm, int k, int level);
+int relin_rescale_one(const mick_params* prm, const mick_keys* keys, int k, int level, int mu, uint32_t* ws,
+                      uint32_t* out, hipStream_t s);
+
 size_t job_ws_bytes(const mick_params* prm, int k, int level);
 size_t table_bytes(int n_jobs);
 int check_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs);

@@ -63,10 +63,14 @@ int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blo
 int launch_kip_b_jt(const mick_params* prm, const JobDesc* jt, int nj, int blocks, const GroupConsts& G,
                     hipStream_t s);
 
-int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout, const MdArgs& A, int mu,
+// Algorithm 1 steps 2-3 over `polys` polynomials ([polys][...] layouts).
+int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout, const MdArgs& A, int mu, int polys,
                    hipStream_t s);
 int launch_rs_combine(const mick_params* prm, const uint32_t* Ain, const uint32_t* Bn, uint32_t* out, const MdArgs& A,
-                      int mu, hipStream_t s);
+                      int mu, int polys, hipStream_t s);
+// Algorithm 1 on polys NTT-domain polynomials (api.hip); ws: polys level N words.
+int rescale_polys(const mick_params* prm, const uint32_t* in, int polys, int level, int mu, uint32_t* out,
+                  uint32_t* ws, hipStream_t s);
 int launch_pk(const mick_params* prm, const uint32_t* E, const uint32_t* a, const uint32_t* S, uint32_t* b,
               hipStream_t s);
 int launch_mul_rows(const mick_params* prm, uint32_t* X, const uint32_t* Y, int rows, hipStream_t s);

@@ -192,7 +192,8 @@ __global__ __launch_bounds__(kThreads) void k_moddown_rs_jt(const JobDesc* jt, i
 }
 
 // Algorithm 1 step 2 and the sums of step 3 on coefficient-domain dropped
-// limbs `topc` ([2][MU][N]): b_eta = sum_t g^{mu,t}_eta a^(t),{l-1-t}.
+// limbs `topc` ([polys][MU][N], polynomial blockIdx.y):
+// b_eta = sum_t g^{mu,t}_eta a^(t),{l-1-t}.
 template <int MU>
 __global__ __launch_bounds__(kThreads) void k_rs_sums(const uint32_t* topc, uint32_t* bout, MdArgs A, DevTables T) {
   const size_t N = (size_t)1 << A.log_n;
@@ -363,9 +364,9 @@ int launch_moddown_rs_jt(const mick_params* prm, const JobDesc* jt, int j0, int 
   return hip_error(hipGetLastError(), "moddown launch");
 }
 
-int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout, const MdArgs& A, int mu,
+int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout, const MdArgs& A, int mu, int polys,
                    hipStream_t s) {
-  dim3 grid((unsigned)(prm->N / kThreads), 2, 1);
+  dim3 grid((unsigned)(prm->N / kThreads), (unsigned)polys, 1);
   const DevTables& T = prm->dt;
   ProfScope ps(P_RS_SUMS, s);
   switch (mu) {
@@ -380,8 +381,8 @@ int launch_rs_sums(const mick_params* prm, const uint32_t* topc, uint32_t* bout,
 }
 
 int launch_rs_combine(const mick_params* prm, const uint32_t* Ain, const uint32_t* Bn, uint32_t* out, const MdArgs& A,
-                      int mu, hipStream_t s) {
-  dim3 grid((unsigned)(prm->N / kThreads), (unsigned)(A.level - mu), 2);
+                      int mu, int polys, hipStream_t s) {
+  dim3 grid((unsigned)(prm->N / kThreads), (unsigned)(A.level - mu), (unsigned)polys);
   ProfScope ps(P_RS_COMBINE, s);
   k_rs_combine<<<grid, kThreads, 0, s>>>(Ain, Bn, out, A, mu, prm->dt);
   return hip_error(hipGetLastError(), "rescale combine launch");

@@ -57,6 +57,12 @@ _SIGS = {
                                       ctypes.POINTER(_vp)]),
     "mick_plan_execute": (ctypes.c_int, [_vp, _vp]),
     "mick_plan_destroy": (None, [_vp]),
+    "mick_tree_plan": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "mick_tree_shape": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "mick_tree_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int]),
+    "mick_mul_tree": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp]),
     "mick_queue_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_size_t,
                                          ctypes.POINTER(_vp)]),
     "mick_queue_job_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
@@ -525,3 +531,79 @@ def use_torch_allocator(on: bool = True):
            "mick_set_allocator")
     # earlier callbacks stay referenced: objects created with them still free through them
     _allocator_refs = (refs, _allocator_refs)
+
+
+# ---------------------------------------------------------------- tree multiply
+
+def tree_tokens(tree) -> list:
+    """Nested tuples (an int: a group of that many inputs; a tuple: a node)
+    to the library's prefix tokens."""
+    if isinstance(tree, int):
+        return [tree]
+    out = [-len(tree)]
+    for c in tree:
+        out += tree_tokens(c)
+    return out
+
+
+def tree_from_tokens(tok) -> object:
+    def rec(i):
+        v = tok[i]
+        if v > 0:
+            return v, i + 1
+        kids, j = [], i + 1
+        for _ in range(-v):
+            c, j = rec(j)
+            kids.append(c)
+        return tuple(kids), j
+    t, end = rec(0)
+    if end != len(tok):
+        raise ValueError("tokens left over")
+    return t
+
+
+def _tok_array(tree):
+    tok = tree_tokens(tree)
+    return (ctypes.c_int * len(tok))(*tok), len(tok)
+
+
+def tree_plan(n: int):
+    """The partition of n inputs with the fewest rescale units at depth
+    ceil(log2 n), as nested tuples."""
+    buf = (ctypes.c_int * 64)()
+    k = load().mick_tree_plan(n, buf, 64)
+    if k < 0:
+        raise MickError(k, "mick_tree_plan")
+    return tree_from_tokens(list(buf[:k]))
+
+
+def tree_shape(tree):
+    """(inputs, depth, rescale units before relinearisation)."""
+    arr, k = _tok_array(tree)
+    n, d, u = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().mick_tree_shape(arr, k, ctypes.byref(n), ctypes.byref(d), ctypes.byref(u)), "mick_tree_shape")
+    return n.value, d.value, u.value
+
+
+def tree_workspace(prm: Params, tree, level: int) -> torch.Tensor:
+    arr, k = _tok_array(tree)
+    nbytes = load().mick_tree_workspace_bytes(prm.handle, arr, k, level)
+    if nbytes == 0:
+        raise ValueError("invalid tree or level")
+    return _dev_empty((nbytes + 3) // 4)
+
+
+def mul_tree(prm: Params, keys: Keys, cts: Sequence[torch.Tensor], level: int, tree, out=None, ws=None):
+    """Tree-structured multiply; returns the [2, level - depth, N] output."""
+    arr, k = _tok_array(tree)
+    n, depth, _ = tree_shape(tree)
+    if len(cts) != n:
+        raise ValueError("the tree takes %d inputs" % n)
+    if out is None:
+        out = _dev_empty(2, level - depth, prm.N)
+    if ws is None:
+        ws = tree_workspace(prm, tree, level)
+    ptrs = (_vp * n)(*[_ptr(c).value for c in cts])
+    _check(load().mick_mul_tree(prm.handle, keys.handle, ptrs, level, arr, k, _ptr(out), _ptr(ws), ws.numel() * 4,
+                                _stream()), "mick_mul_tree")
+    return out

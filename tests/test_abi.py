@@ -79,3 +79,32 @@ def test_queue_schedule_allocator_validate_without_gpu():
     cb = ctypes.CFUNCTYPE(vp, ctypes.c_size_t, vp)(lambda n, c: None)
     assert lib.mick_set_allocator(ctypes.cast(cb, vp), None, None) == -1
     assert lib.mick_set_allocator(None, None, None) == 0
+
+
+def test_tree_planner_and_shapes_without_gpu():
+    """The library's planner and shape report (host code) against the oracle's
+    planner and Table II counting."""
+    from oracle import tree as T
+    from paper_2601_15401_amd import mick
+    for n in range(2, 18):
+        got = mick.tree_plan(n)
+        assert got == T.plan(n), n
+        assert mick.tree_shape(got) == (n, T.depth(got), T.rs_units(got)[0])
+        b = T.binary_plan(n)
+        assert mick.tree_shape(b) == (n, T.depth(b), T.rs_units(b)[0])
+    for t in [(2, 2, 2), ((3, 2), 1), (1, 1), 5, ((2, 2), (2, 1))]:
+        assert mick.tree_shape(t) == (T.n_inputs(t), T.depth(t), T.rs_units(t)[0])
+    lib = ctypes.CDLL(LIB)
+    arr = (ctypes.c_int * 3)(-2, 2, 0)
+    assert lib.mick_tree_shape(arr, 3, None, None, None) == -1          # group of 0
+    arr = (ctypes.c_int * 2)(-2, 2)
+    assert lib.mick_tree_shape(arr, 2, None, None, None) == -1          # missing child
+    arr = (ctypes.c_int * 3)(2, 2, 2)
+    assert lib.mick_tree_shape(arr, 3, None, None, None) == -1          # tokens left over
+    arr = (ctypes.c_int * 2)(-1, 2)
+    assert lib.mick_tree_shape(arr, 2, None, None, None) == -1          # node of one child
+    arr = (ctypes.c_int * 1)(-(1 << 31))
+    assert lib.mick_tree_shape(arr, 1, None, None, None) == -1
+    buf = (ctypes.c_int * 2)()
+    assert lib.mick_tree_plan(12, buf, 2) == -1                         # too few token slots
+    assert lib.mick_tree_plan(1, buf, 2) == -1

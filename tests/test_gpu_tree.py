@@ -1,0 +1,97 @@
+"""Tree-structured multiply on the GPU against the oracle's tree multiply,
+bit for bit, and at the full N = 2^16 shape through decryption."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ckks, keys as okeys, params as oparams, tree as T
+from paper_2601_15401_amd import mick
+
+pytestmark = pytest.mark.gpu
+
+SCALE = 2.0 ** 30
+
+
+class Ctx:
+    def __init__(self, log_n, L, K, dnum, seed, k_max):
+        self.op = oparams.make_params(log_n, L, K, dnum)
+        self.ok = okeys.keygen(self.op, seed, k_max)
+        self.prm = mick.Params(log_n, L, K, dnum)
+        self.gk = mick.Keys(self.prm, seed, k_max)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return Ctx(13, 8, 2, 4, 77, 12)
+
+
+def _rand(rng, op, level):
+    return np.stack([np.stack([rng.integers(0, q, op.N, dtype=np.int64).astype(np.uint64) for q in op.q[:level]])
+                     for _ in range(2)])
+
+
+@pytest.mark.parametrize("tree,level", [
+    ((2, 2), 8), ((2, 2, 1), 8), ((3, (1, 1)), 8), (((2, 2), 3), 8), ((3, 3), 8), ((1, 1), 8), (4, 8),
+    (((2, 1), (1, 1, 1)), 8), (((2, 2), (2, 2)), 8), ((2, 2, 1), 5), (((2, 2), 3), 4), ((1, 1, 1), 3),
+    (((3, 3), (3, 3)), 8), (((2, 2), (2, 2), 3), 8), ((3, 3, 3), 6),
+])
+def test_tree_matches_oracle(ctx, tree, level):
+    n = T.n_inputs(tree)
+    rng = np.random.default_rng(1000 + 7 * n + level)
+    host = [_rand(rng, ctx.op, level) for _ in range(n)]
+    dev = [mick.from_numpy_u32(h.astype(np.uint32)) for h in host]
+    got = mick.mul_tree(ctx.prm, ctx.gk, dev, level, tree)
+    want, lvl, _ = T.mul_tree(ctx.op, ctx.ok, host, level, tree)
+    assert got.shape == (2, lvl, ctx.op.N)
+    g = mick.to_numpy_u32(got).astype(np.uint64)
+    bad = np.argwhere(g != want)
+    assert bad.size == 0, "%s: %d residues differ, first at %s" % (tree, len(bad), bad[0].tolist())
+
+
+def test_flat_tree_is_the_flat_multiply(ctx):
+    rng = np.random.default_rng(5)
+    dev = [mick.from_numpy_u32(_rand(rng, ctx.op, 8).astype(np.uint32)) for _ in range(5)]
+    flat = mick.mul_relin_rescale(ctx.prm, ctx.gk, dev, 8)
+    assert torch.equal(mick.mul_tree(ctx.prm, ctx.gk, dev, 8, 5), flat)
+    assert torch.equal(mick.mul_tree(ctx.prm, ctx.gk, dev, 8, (1, 1, 1, 1, 1)), flat)
+
+
+def test_tree_errors(ctx):
+    rng = np.random.default_rng(6)
+    dev = [mick.from_numpy_u32(_rand(rng, ctx.op, 3).astype(np.uint32)) for _ in range(4)]
+    with pytest.raises(ValueError):  # depth 2 needs level >= 3; (2,2) at level 2: no workspace size
+        mick.mul_tree(ctx.prm, ctx.gk, [d[:, :2].contiguous() for d in dev], 2, (2, 2))
+    small = mick.Keys(ctx.prm, 78, 4)
+    five = [mick.from_numpy_u32(_rand(rng, ctx.op, 8).astype(np.uint32)) for _ in range(5)]
+    with pytest.raises(mick.MickError):  # keys only up to s^4
+        mick.mul_tree(ctx.prm, small, five, 8, (2, 2, 1))
+
+
+def test_six_input_tree_n16_matches_oracle_and_decodes():
+    """(3, 3) at the full N = 2^16, 32 + 8 primes: bit for bit the oracle's
+    tree multiply, and decoding to the product of the six messages.  (Trees
+    whose internal nodes rescale polynomials of degree 4 and more lose
+    precision at scale 2^30: the floor rescale of component t is multiplied
+    by s^t; their exactness is checked at N = 2^13 above.)"""
+    op = oparams.preset(16)
+    ok = okeys.keygen(op, 12, 6)
+    prm = mick.Params(16, op.L, op.K, op.dnum)
+    gk = mick.Keys(prm, 12, 6)
+    tree = (3, 3)
+    level = op.L
+    cts_o, cts_g, want = [], [], np.ones(op.N // 2, dtype=np.complex128)
+    for u in range(6):
+        r, i, m = ckks.message(op, 12, u, SCALE)
+        want = want * (r + 1j * i)
+        cts_o.append(ckks.encrypt(op, ok, m, level, 12, u))
+        cts_g.append(mick.encrypt(prm, gk, m, level, 12, u))
+    out = mick.mul_tree(prm, gk, cts_g, level, tree)
+    ref, lvl, dropped = T.mul_tree(op, ok, cts_o, level, tree)
+    assert lvl == 29 and out.shape == (2, lvl, op.N)
+    assert np.array_equal(mick.to_numpy_u32(out).astype(np.uint64), ref)
+    scale_out = SCALE ** 6
+    for q in dropped:
+        scale_out /= q
+    re, im = mick.decode(prm, mick.decrypt(prm, gk, out, lvl), scale_out)
+    err = np.abs((re + 1j * im) - want)
+    assert err.max() < 1e-2, err.max()
