@@ -40,6 +40,7 @@ WORKLOADS = {
     "n13_k3": (13, 3, 1, 3, 3, 3, 1),
     "mixed512": None,  # heterogeneous batch, see run_mixed
     "serve5000": None,  # open-loop serving, see run_serve
+    "trees": None,  # flat / planned tree / binary tree of two-input multiplies, see run_trees
 }
 # parameter sets of the mixed workload: log_n -> (L, K, dnum)
 MIXED_PARAMS = {13: (3, 1, 3), 14: (8, 2, 4), 15: (16, 4, 4), 16: (32, 8, 4)}
@@ -453,6 +454,146 @@ def run_serve(args, torch, mick):
     print(json.dumps(rec), flush=True)
 
 
+def relin_transforms(k, level, mu, K, alpha):
+    """(I)NTT limb transforms of one relinearise-and-rescale of a degree-k
+    product at `level` with mu rescales: INTT of d_2..d_k, NTT of the ModUp
+    outputs, INTT of the accumulators, NTT of the output."""
+    B = -(-level // alpha)
+    return (k - 1) * B * (level + K) + 2 * K + 4 * level - 2 * mu
+
+
+def run_trees(args, torch, mick):
+    """n = 3..12 inputs at N = 2^16 (32 + 8 primes, dnum 4): the flat multiply
+    (depth n - 1), the planned tree of Sec. V-C (depth ceil(log2 n)) and a
+    binary tree of two-input multiplies each with its own relinearisation and
+    rescale (the paper's baseline, same depth).  Per method: time per
+    multiply (single launches, HIP events), output level, limb transforms,
+    key bytes read, and the largest slot error of the decoded product."""
+    log_n, L, K, dnum = 16, 32, 8, 4
+    prm = mick.Params(log_n, L, K, dnum)
+    keys = mick.Keys(prm, 21, 12)
+    N, alpha = prm.N, prm.alpha
+    scale = 2.0 ** 30
+    rng = np.random.default_rng(21)
+    cts, zs = [], []
+    for u in range(12):
+        re, im = rng.uniform(-1, 1, N // 2), rng.uniform(-1, 1, N // 2)
+        zs.append(re + 1j * im)
+        cts.append(mick.encrypt(prm, keys, mick.encode(prm, re, im, scale), L, 21, u))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps
+
+    def error(out, level, dropped_levels, n):
+        sc = scale ** n
+        for j in dropped_levels:
+            sc /= prm.q[j]
+        re, im = mick.decode(prm, mick.decrypt(prm, keys, out, level), sc)
+        want = np.prod(np.stack(zs[:n]), axis=0)
+        return float(np.abs(re + 1j * im - want).max())
+
+    def key_bytes(k, level):
+        return (k - 1) * (-(-level // alpha)) * 2 * (level + K) * N * 4
+
+    def binary(tree, inputs, end):
+        """Evaluates the binary tree with two-input multiplies; returns
+        (ciphertext at level `end`, transforms, key bytes, dropped levels)."""
+        if isinstance(tree, int):
+            if tree == 1:
+                c = inputs.pop(0)
+                return c[:, :end].contiguous() if c.shape[1] != end else c, 0, 0, []
+            a, b = inputs.pop(0), inputs.pop(0)
+            lv = end + 1
+            a, b = a[:, :lv].contiguous(), b[:, :lv].contiguous()
+            return (mick.mul_relin_rescale(prm, keys, [a, b], lv), relin_transforms(2, lv, 1, K, alpha),
+                    key_bytes(2, lv), [lv - 1])
+        lv = end + 1
+        parts = [binary(c, inputs, lv) for c in tree]
+        out = mick.mul_relin_rescale(prm, keys, [p[0] for p in parts], lv)
+        return (out, sum(p[1] for p in parts) + relin_transforms(2, lv, 1, K, alpha),
+                sum(p[2] for p in parts) + key_bytes(2, lv), sum((p[3] for p in parts), []) + [lv - 1])
+
+    def binary_plan(n):
+        if n <= 2:
+            return n
+        p = 1 << (math.ceil(math.log2(n)) - 1)
+        return (binary_plan(p), binary_plan(n - p))
+
+    rows = []
+    for n in range(3, 13):
+        row = {"n": n}
+        # flat
+        out, ms = timed(lambda: mick.mul_relin_rescale(prm, keys, cts[:n], L))
+        lv = L - n + 1
+        row["flat"] = {"ms": round(ms, 3), "out_level": lv, "transforms": relin_transforms(n, L, n - 1, K, alpha),
+                       "key_MB": round(key_bytes(n, L) / 1e6, 1),
+                       "max_err": error(out, lv, list(range(lv, L)), n)}
+        # planned tree
+        tree = mick.tree_plan(n)
+        ws = mick.tree_workspace(prm, tree, L)
+        _, depth, units = mick.tree_shape(tree)
+        lv = L - depth
+        out_t = torch.empty(2, lv, N, dtype=torch.int32, device="cuda")
+        out, ms = timed(lambda: mick.mul_tree(prm, keys, cts[:n], L, tree, out=out_t, ws=ws))
+        resc = mick.tree_rescales(tree, L)
+        root_prod, root_mu = resc[-1]
+        pre = 0
+        nodes = []
+
+        def deg_walk(t):  # polynomials rescaled per node, post-order like tree_rescales
+            if isinstance(t, int):
+                if t > 1:
+                    nodes.append(t + 1)
+                return t
+            d = sum(deg_walk(c) for c in t)
+            nodes.append(d + 1)
+            return d
+        deg_walk(tree)
+        for (prod, mu), npoly in zip(resc[:-1], nodes[:-1]):
+            pre += npoly * prod  # Algorithm 1: mu INTT + (prod - mu) NTT per polynomial
+        drops = [j for prod, mu in resc for j in range(prod - mu, prod)]
+        row["tree"] = {"partition": str(tree), "ms": round(ms, 3), "out_level": lv, "rs_units": units,
+                       "transforms": pre + relin_transforms(n, root_prod, root_mu, K, alpha),
+                       "key_MB": round(key_bytes(n, root_prod) / 1e6, 1), "max_err": error(out, lv, drops, n)}
+        del ws
+        # binary tree of two-input multiplies
+        bt = binary_plan(n)
+        res, ms = timed(lambda: binary(bt, list(cts[:n]), L - _depth(bt)))
+        out, tr, kb, dropped = res
+        row["binary"] = {"partition": str(bt), "ms": round(ms, 3), "out_level": L - _depth(bt), "transforms": tr,
+                         "key_MB": round(kb / 1e6, 1), "max_err": error(out, L - _depth(bt), dropped, n)}
+        log("n=%2d flat %7.3f ms (level %2d, err %.1e) | tree %-22s %7.3f ms (level %2d, err %.1e) | "
+            "binary %7.3f ms (err %.1e)" % (n, row["flat"]["ms"], row["flat"]["out_level"], row["flat"]["max_err"],
+                                            str(tree), row["tree"]["ms"], row["tree"]["out_level"],
+                                            row["tree"]["max_err"], row["binary"]["ms"], row["binary"]["max_err"]))
+        rows.append(row)
+    r12 = rows[-1]
+    rec = {
+        "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
+        "value": round(1e3 / r12["tree"]["ms"], 2), "unit": "ct-mults/s", "n_gpus": 1, "steps": 5, "warmup": 1,
+        "ms_per_step": r12["tree"]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "n-input multiplies n=3..12 at N=2^16, 32+8 primes, dnum=4: flat, planned tree, "
+                               "binary tree of two-input multiplies (value: planned 12-input tree, one at a time)",
+                   "parallelism": "none"},
+        "rows": rows, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def _depth(t):
+    return t - 1 if isinstance(t, int) else max(_depth(c) for c in t) + len(t) - 1
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,8 +603,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=3)
-    ap.add_argument("--serve-streams", type=int, default=2, help="serve5000: concurrent micro-batches")
-    ap.add_argument("--serve-max-batch", type=int, default=256, help="serve5000: most requests per micro-batch")
+    ap.add_argument("--serve-streams", type=int, default=4, help="serve5000: concurrent micro-batches")
+    ap.add_argument("--serve-max-batch", type=int, default=32, help="serve5000: most requests per micro-batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized buffer once before timing (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -480,6 +621,9 @@ def main():
         return
     if args.workload == "serve5000":
         run_serve(args, torch, mick)
+        return
+    if args.workload == "trees":
+        run_trees(args, torch, mick)
         return
     log_n, L, K, dnum, k, level, jobs = WORKLOADS[args.workload]
     log("params N=2^%d L=%d K=%d dnum=%d; keygen k_max=%d ..." % (log_n, L, K, dnum, k))

@@ -585,6 +585,31 @@ def tree_shape(tree):
     return n.value, d.value, u.value
 
 
+def _tree_depth(t) -> int:
+    if isinstance(t, int):
+        return t - 1
+    return max(_tree_depth(c) for c in t) + len(t) - 1
+
+
+def tree_rescales(tree, level: int):
+    """[(product level, mu)] of every rescale the tree performs on inputs at
+    `level` (every subtree runs at the level at which it enters its parent);
+    the output scale is Delta^n over the product of the primes q_j with
+    product level - mu <= j < product level over all entries."""
+    out = []
+
+    def walk(t, end):
+        mu = (t if isinstance(t, int) else len(t)) - 1
+        prod = end + mu
+        if not isinstance(t, int):
+            for c in t:
+                walk(c, prod)
+        if mu > 0:
+            out.append((prod, mu))
+    walk(tree, level - _tree_depth(tree))
+    return out
+
+
 def tree_workspace(prm: Params, tree, level: int) -> torch.Tensor:
     arr, k = _tok_array(tree)
     nbytes = load().mick_tree_workspace_bytes(prm.handle, arr, k, level)
