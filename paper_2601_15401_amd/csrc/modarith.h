@@ -42,6 +42,14 @@ __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, uint32_t m,
   return min(r + m, r);
 }
 
+// Montgomery reduction of T < m 2^32: T 2^-32 mod m in [0, m).  As in
+// mont_mul, the quotient lies in (-m, m) and min(r + m, r) corrects it.
+__device__ __forceinline__ uint32_t redc(uint64_t T, uint32_t m, uint32_t minv) {
+  const uint32_t lo = (uint32_t)T, hi = (uint32_t)(T >> 32);
+  const uint32_t r = hi - __umulhi(lo * minv, m);
+  return min(r + m, r);
+}
+
 // Montgomery reduction of T < 2m 2^32: T 2^-32 mod m in [0, m).  The
 // quotient hi - mh lies in (-m, 2m) here; r + m would overflow 32 bits for
 // m near 2^31, so the negative case is detected by comparing hi and mh.

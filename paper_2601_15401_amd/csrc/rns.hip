@@ -36,17 +36,20 @@ __device__ __forceinline__ void tensor_body(const uint32_t* const (&inp)[K], int
   for (int u = 1; u < K; u++) {
     const uint4 a = reinterpret_cast<const uint4*>(inp[u] + limb)[n];
     const uint4 b = reinterpret_cast<const uint4*>(inp[u] + poly + limb)[n];
-    // new_t = P_t a + P_{t-1} b, t = u+1 .. 0 (descending keeps P_{t-1} intact)
+    // new_t = P_t a + P_{t-1} b, t = u+1 .. 0 (descending keeps P_{t-1} intact).
+    // The two products of canonical residues are summed exactly (below
+    // 2 m^2 < m 2^32) and reduced once: the same residue, with the same
+    // factor R^-1, as two Montgomery products and a modular add.
     P[u + 1].x = mont_mul(P[u].x, b.x, m, minv);
     P[u + 1].y = mont_mul(P[u].y, b.y, m, minv);
     P[u + 1].z = mont_mul(P[u].z, b.z, m, minv);
     P[u + 1].w = mont_mul(P[u].w, b.w, m, minv);
 #pragma unroll
     for (int t = u; t >= 1; t--) {
-      P[t].x = add_mod(mont_mul(P[t].x, a.x, m, minv), mont_mul(P[t - 1].x, b.x, m, minv), m);
-      P[t].y = add_mod(mont_mul(P[t].y, a.y, m, minv), mont_mul(P[t - 1].y, b.y, m, minv), m);
-      P[t].z = add_mod(mont_mul(P[t].z, a.z, m, minv), mont_mul(P[t - 1].z, b.z, m, minv), m);
-      P[t].w = add_mod(mont_mul(P[t].w, a.w, m, minv), mont_mul(P[t - 1].w, b.w, m, minv), m);
+      P[t].x = redc((uint64_t)P[t].x * a.x + (uint64_t)P[t - 1].x * b.x, m, minv);
+      P[t].y = redc((uint64_t)P[t].y * a.y + (uint64_t)P[t - 1].y * b.y, m, minv);
+      P[t].z = redc((uint64_t)P[t].z * a.z + (uint64_t)P[t - 1].z * b.z, m, minv);
+      P[t].w = redc((uint64_t)P[t].w * a.w + (uint64_t)P[t - 1].w * b.w, m, minv);
     }
     P[0].x = mont_mul(P[0].x, a.x, m, minv);
     P[0].y = mont_mul(P[0].y, a.y, m, minv);
