@@ -102,64 +102,115 @@ __global__ __launch_bounds__(kThreads) void k_tensor_jt(const JobDesc* jt, int j
 // eq. (multi rs): the dropped limbs run the chain of Algorithm 1 step 2,
 // every kept limb eta takes g^{mu,l-1}_eta c*_eta - sum_t g^{mu,t}_eta a_t.
 // Output coefficient domain, limbs 0..l-mu-1 (the final NTT follows).
+// Constants of one launch staged in LDS (every thread reads them with
+// uniform addresses): phat_i^-1 (+Shoup) [K][2], p_i^-1 mod q_j [K][level],
+// the chain's q_d^-1 mod q_t (+Shoup) [MU][MU][2], g^{mu,l-1}_eta (+Shoup)
+// [top][2] and g^{mu,t}_eta [top][MU].
+constexpr int kMdLdsWords = 2 * kMaxKp + kMaxKp * 60 + 2 * 12 * 12 + 2 * 60 + 60 * 12;
+
+template <int MU>
+__device__ __forceinline__ void moddown_stage(const MdArgs& A, uint32_t* c) {
+  const int top = A.level - MU;
+  uint32_t* phinv = c;
+  uint32_t* pinvq = phinv + 2 * kMaxKp;
+  uint32_t* chain = pinvq + kMaxKp * 60;
+  uint32_t* gtop = chain + 2 * 12 * 12;
+  uint32_t* gt = gtop + 2 * 60;
+  // rows i >= K are zero, so the loops over the special primes need no bounds
+  for (int i = threadIdx.x; i < 2 * kMaxKp; i += kThreads) phinv[i] = i < 2 * A.K ? A.md[i] : 0u;
+  for (int i = threadIdx.x; i < kMaxKp * A.level; i += kThreads) {
+    const int pi = i / A.level, j = i - pi * A.level;
+    pinvq[i] = pi < A.K ? A.md[2 * A.K + (size_t)pi * A.L + j] : 0u;
+  }
+  if constexpr (MU > 0) {
+    for (int i = threadIdx.x; i < MU * MU; i += kThreads) {
+      const int u = i / MU, t = i - u * MU;  // rescale u drops q_{l-u}; limb top + t
+      if (u >= 1 && t < MU - u) {
+        const uint32_t* ci = A.qinvq + 2 * ((size_t)(A.level - u) * A.L + top + t);
+        chain[2 * i] = ci[0];
+        chain[2 * i + 1] = ci[1];
+      }
+    }
+    for (int i = threadIdx.x; i < 2 * top; i += kThreads) gtop[i] = A.rs[i];
+    for (int i = threadIdx.x; i < top * MU; i += kThreads) gt[i] = A.rs[2 * top + i];
+  }
+  __syncthreads();
+}
+
 template <int MU>
 __device__ __forceinline__ void moddown_body(const uint32_t* acc, uint32_t* out, const MdArgs& A, int l, size_t n,
-                                             const DevTables& T) {
+                                             const uint32_t* c, const DevTables& T) {
   const size_t N = (size_t)1 << A.log_n;
   const uint32_t* row = acc + (size_t)l * A.E * N + n;
   uint32_t* o = out + (size_t)l * (A.level - MU) * N + n;
-  // scaled p residues z_i = [phat_i^-1 x_i]_{p_i}
+  const uint32_t* phinv = c;
+  const uint32_t* pinvq = phinv + 2 * kMaxKp;
+  const uint32_t* chain = pinvq + kMaxKp * 60;
+  const uint32_t* gtop = chain + 2 * 12 * 12;
+  const uint32_t* gt = gtop + 2 * 60;
+  // scaled p residues z_i = [phat_i^-1 x_i]_{p_i}; for i >= K the staged
+  // constant is 0 (and the row read is the last special prime's)
   uint32_t z[kMaxKp];
 #pragma unroll
   for (int i = 0; i < kMaxKp; i++) {
-    if (i < A.K) {
-      const uint32_t pi = T.mod[A.L + i];
-      z[i] = shoup(row[(size_t)(A.level + i) * N], A.md[2 * i], A.md[2 * i + 1], pi);
-    }
+    const int ii = min(i, A.K - 1);
+    z[i] = shoup(row[(size_t)(A.level + ii) * N], phinv[2 * i], phinv[2 * i + 1], T.mod[A.L + ii]);
   }
-  const uint32_t* pinvq = A.md + 2 * A.K;  // [K][L]
-  auto cstar = [&](int j) -> uint32_t {
+  auto cstar = [&](int j, uint32_t x) -> uint32_t {
     const Red64 rc = T.red[j];
     uint64_t s = 0;
 #pragma unroll
-    for (int i = 0; i < kMaxKp; i++) {
-      if (i < A.K) s += (uint64_t)z[i] * pinvq[(size_t)i * A.L + j];
-    }
-    return sub_mod(row[(size_t)j * N], reduce64(s, rc), rc.m);
+    for (int i = 0; i < kMaxKp; i++) s += (uint64_t)z[i] * pinvq[i * A.level + j];
+    return sub_mod(x, reduce64(s, rc), rc.m);
   };
   if constexpr (MU == 0) {
-    for (int j = 0; j < A.level; j++) o[(size_t)j * N] = cstar(j);
+    for (int j = 0; j < A.level; j++) o[(size_t)j * N] = cstar(j, row[(size_t)j * N]);
   } else {
     const int top = A.level - MU;
     uint32_t fin[MU];
     {
       uint32_t cur[MU];
 #pragma unroll
-      for (int i = 0; i < MU; i++) cur[i] = cstar(top + i);
+      for (int i = 0; i < MU; i++) cur[i] = row[(size_t)(top + i) * N];
+#pragma unroll
+      for (int i = 0; i < MU; i++) cur[i] = cstar(top + i, cur[i]);
       fin[MU - 1] = cur[MU - 1];
-      // the u-th rescale drops q_{l-u}; chain constants q_d^-1 mod q_t (+ Shoup)
+      // the u-th rescale drops q_{l-u}
 #pragma unroll
       for (int u = 1; u < MU; u++) {
-        const int d = A.level - u;
         const uint32_t cd = cur[MU - u];
 #pragma unroll
         for (int i = 0; i < MU - u; i++) {
-          const int t = top + i;
-          const uint32_t qt = T.mod[t];
-          const uint32_t* ci = A.qinvq + 2 * ((size_t)d * A.L + t);
+          const uint32_t qt = T.mod[top + i];
+          const uint32_t* ci = chain + 2 * (u * MU + i);
           cur[i] = shoup(cur[i] + qt - cd, ci[0], ci[1], qt);
         }
         fin[MU - 1 - u] = cur[MU - 1 - u];
       }
     }
-    const uint32_t* g = A.rs;  // [top][2] gtop (+Shoup), then [top][MU] g
-    const uint32_t* gt = g + 2 * (size_t)top;
-    for (int eta = 0; eta < top; eta++) {
+    // four output limbs per round: their loads issue together
+    int eta = 0;
+    for (; eta + 4 <= top; eta += 4) {
+      uint32_t x[4];
+#pragma unroll
+      for (int v = 0; v < 4; v++) x[v] = row[(size_t)(eta + v) * N];
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int e = eta + v;
+        const Red64 rc = T.red[e];
+        uint64_t s = 0;
+#pragma unroll
+        for (int i = 0; i < MU; i++) s += (uint64_t)fin[i] * gt[e * MU + i];
+        const uint32_t a = shoup(cstar(e, x[v]), gtop[2 * e], gtop[2 * e + 1], rc.m);
+        o[(size_t)e * N] = sub_mod(a, reduce64(s, rc), rc.m);
+      }
+    }
+    for (; eta < top; eta++) {
       const Red64 rc = T.red[eta];
       uint64_t s = 0;
 #pragma unroll
-      for (int i = 0; i < MU; i++) s += (uint64_t)fin[i] * gt[(size_t)eta * MU + i];
-      const uint32_t a = shoup(cstar(eta), g[2 * eta], g[2 * eta + 1], rc.m);
+      for (int i = 0; i < MU; i++) s += (uint64_t)fin[i] * gt[eta * MU + i];
+      const uint32_t a = shoup(cstar(eta, row[(size_t)eta * N]), gtop[2 * eta], gtop[2 * eta + 1], rc.m);
       o[(size_t)eta * N] = sub_mod(a, reduce64(s, rc), rc.m);
     }
   }
@@ -167,9 +218,11 @@ __device__ __forceinline__ void moddown_body(const uint32_t* acc, uint32_t* out,
 
 template <int MU>
 __global__ __launch_bounds__(kThreads) void k_moddown_rs(const uint32_t* acc, uint32_t* out, MdArgs A, DevTables T) {
+  __shared__ uint32_t c[kMdLdsWords];
+  moddown_stage<MU>(A, c);
   const size_t job = blockIdx.z;
   moddown_body<MU>(acc + job * (size_t)A.acc_job, out + job * (size_t)A.out_job, A, blockIdx.y,
-                   (size_t)blockIdx.x * kThreads + threadIdx.x, T);
+                   (size_t)blockIdx.x * kThreads + threadIdx.x, c, T);
 }
 
 // Job-table form: jobs [j0, j0 + nj) of equal k = MU + 1; blocks per job 2 N / 256.
@@ -191,7 +244,10 @@ __global__ __launch_bounds__(kThreads) void k_moddown_rs_jt(const JobDesc* jt, i
   A.K = G.K;
   A.E = level + G.K;
   const WsLayout lay(MU + 1, level, G.K, G.alpha, G.log_n);
-  moddown_body<MU>(jt[j].ws + lay.acc, jt[j].out, A, local / xb, (size_t)(local % xb) * kThreads + threadIdx.x, T);
+  __shared__ uint32_t c[kMdLdsWords];
+  moddown_stage<MU>(A, c);
+  moddown_body<MU>(jt[j].ws + lay.acc, jt[j].out, A, local / xb, (size_t)(local % xb) * kThreads + threadIdx.x, c,
+                   T);
 }
 
 // Algorithm 1 step 2 and the sums of step 3 on coefficient-domain dropped
