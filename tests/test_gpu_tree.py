@@ -95,3 +95,25 @@ def test_six_input_tree_n16_matches_oracle_and_decodes():
     re, im = mick.decode(prm, mick.decrypt(prm, gk, out, lvl), scale_out)
     err = np.abs((re + 1j * im) - want)
     assert err.max() < 1e-2, err.max()
+
+
+def test_twelve_input_flat_n16_decodes():
+    """The heaviest multiply served (N = 2^16, k = 12, keys up to s^12, 11
+    rescales): decoding gives the product of the twelve messages."""
+    op = oparams.preset(16)
+    prm = mick.Params(16, op.L, op.K, op.dnum)
+    gk = mick.Keys(prm, 13, 12)
+    level = op.L
+    cts, want = [], np.ones(op.N // 2, dtype=np.complex128)
+    for u in range(12):
+        r, i, m = ckks.message(op, 13, u, SCALE)
+        want = want * (r + 1j * i)
+        cts.append(mick.encrypt(prm, gk, m, level, 13, u))
+    out = mick.mul_relin_rescale(prm, gk, cts, level)
+    lvl = level - 11
+    scale_out = SCALE ** 12
+    for t in range(lvl, level):
+        scale_out /= op.q[t]
+    re, im = mick.decode(prm, mick.decrypt(prm, gk, out, lvl), scale_out)
+    err = np.abs((re + 1j * im) - want)
+    assert err.max() < 1e-2, err.max()
