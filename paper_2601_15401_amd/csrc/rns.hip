@@ -252,9 +252,25 @@ __global__ __launch_bounds__(kThreads) void k_moddown_rs_jt(const JobDesc* jt, i
 
 // Algorithm 1 step 2 and the sums of step 3 on coefficient-domain dropped
 // limbs `topc` ([polys][MU][N], polynomial blockIdx.y):
-// b_eta = sum_t g^{mu,t}_eta a^(t),{l-1-t}.
+// b_eta = sum_t g^{mu,t}_eta a^(t),{l-1-t}.  The chain constants and the g
+// table are staged in LDS.
 template <int MU>
 __global__ __launch_bounds__(kThreads) void k_rs_sums(const uint32_t* topc, uint32_t* bout, MdArgs A, DevTables T) {
+  __shared__ uint32_t chain[2 * MU * MU];  // [u][t][2], rescale u dropping q_{l-u}
+  __shared__ uint32_t gt[60 * MU];         // [top <= 60][MU]
+  {
+    const int top = A.level - MU;
+    for (int i = threadIdx.x; i < MU * MU; i += kThreads) {
+      const int u = i / MU, t = i - u * MU;
+      if (u >= 1 && t < MU - u) {
+        const uint32_t* ci = A.qinvq + 2 * ((size_t)(A.level - u) * A.L + top + t);
+        chain[2 * i] = ci[0];
+        chain[2 * i + 1] = ci[1];
+      }
+    }
+    for (int i = threadIdx.x; i < top * MU; i += kThreads) gt[i] = A.rs[2 * top + i];
+    __syncthreads();
+  }
   const size_t N = (size_t)1 << A.log_n;
   const size_t n = (size_t)blockIdx.x * kThreads + threadIdx.x;
   const int l = blockIdx.y;
@@ -267,22 +283,29 @@ __global__ __launch_bounds__(kThreads) void k_rs_sums(const uint32_t* topc, uint
   fin[MU - 1] = cur[MU - 1];
 #pragma unroll
   for (int u = 1; u < MU; u++) {
-    const int d = A.level - u;
     const uint32_t cd = cur[MU - u];
 #pragma unroll
     for (int i = 0; i < MU - u; i++) {
-      const int t = top + i;
-      const uint32_t qt = T.mod[t];
-      const uint32_t* ci = A.qinvq + 2 * ((size_t)d * A.L + t);
+      const uint32_t qt = T.mod[top + i];
+      const uint32_t* ci = chain + 2 * (u * MU + i);
       cur[i] = shoup(cur[i] + qt - cd, ci[0], ci[1], qt);
     }
     fin[MU - 1 - u] = cur[MU - 1 - u];
   }
-  const uint32_t* gt = A.rs + 2 * (size_t)top;
-  for (int eta = 0; eta < top; eta++) {
+  int eta = 0;
+  for (; eta + 4 <= top; eta += 4) {
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      uint64_t s = 0;
+#pragma unroll
+      for (int i = 0; i < MU; i++) s += (uint64_t)fin[i] * gt[(eta + v) * MU + i];
+      o[(size_t)(eta + v) * N] = reduce64(s, T.red[eta + v]);
+    }
+  }
+  for (; eta < top; eta++) {
     uint64_t s = 0;
 #pragma unroll
-    for (int i = 0; i < MU; i++) s += (uint64_t)fin[i] * gt[(size_t)eta * MU + i];
+    for (int i = 0; i < MU; i++) s += (uint64_t)fin[i] * gt[eta * MU + i];
     o[(size_t)eta * N] = reduce64(s, T.red[eta]);
   }
 }
