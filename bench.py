@@ -38,6 +38,8 @@ WORKLOADS = {
     "n16_k8_b8": (16, 32, 8, 4, 8, 32, 8),
     "n15_k4_b16": (15, 16, 4, 4, 4, 16, 16),
     "n13_k3": (13, 3, 1, 3, 3, 3, 1),
+    # the paper's own setting (Sec. VI): one key-switching digit, K = L = 24
+    "paper3": (16, 24, 24, 1, 3, 24, 8),
     "mixed512": None,  # heterogeneous batch, see run_mixed
     "serve5000": None,  # open-loop serving, see run_serve
     "trees": None,  # flat / planned tree / binary tree of two-input multiplies, see run_trees
@@ -331,6 +333,7 @@ def run_mixed(args, torch, mick):
                    "parallelism": "none"},
         "plain": plain,
         "batched_over_plain": round(value / plain["value"], 3) if plain else None,
+        **({"unfused": unfused} if unfused else {}),
         "queue": {"value": round(n_jobs / (q_ms / 1e3), 2), "unit": "ct-mults/s", "ms_per_512_wall": round(q_ms, 3)},
         "schedules": schedules,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
@@ -680,9 +683,9 @@ def main():
         rl["traffic"] = measured_traffic(rl["kernel"])
 
     plain = None
+    lists = [[cts[j, u] for u in range(k)] for j in range(jobs)]
     if not args.no_plain:
         ws1 = mick.workspace(prm, mick.OP_MUL_RELIN_RESCALE, k, level)
-        lists = [[cts[j, u] for u in range(k)] for j in range(jobs)]
         for j in range(jobs):
             mick.mul_relin_rescale(prm, keys, lists[j], level, out=out[j], ws=ws1)
         torch.cuda.synchronize()
@@ -696,6 +699,36 @@ def main():
         pms = e0.elapsed_time(e1) / (args.steps * jobs)
         plain = {"value": round(1e3 / pms, 2), "unit": "ct-mults/s", "ms_per_mult": round(pms, 4)}
         log("plain: %.3f ms per multiply, %.1f ct-mults/s" % (pms, 1e3 / pms))
+
+    unfused = None
+    if args.workload == "paper3" and not args.no_plain:
+        # the same multiply without relocation: tensor product, relinearisation
+        # with its own ModDown back to the NTT domain, then the (k-1)-level
+        # rescale of Algorithm 1 as a separate call
+        d = torch.empty(k + 1, level, N, dtype=torch.int32, device="cuda")
+        y = torch.empty(2, level, N, dtype=torch.int32, device="cuda")
+        wsr = mick.workspace(prm, mick.OP_RELIN, k, level)
+        wss = mick.workspace(prm, mick.OP_RESCALE, k - 1, level)
+
+        def unfused_one(j):
+            mick.mul_k(prm, lists[j], level, out=d)
+            mick.relin_k(prm, keys, d, k, level, out=y, ws=wsr)
+            mick.rescale_multi(prm, y, level, k - 1, out=out[j], ws=wss)
+
+        for j in range(jobs):
+            unfused_one(j)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            for j in range(jobs):
+                unfused_one(j)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ums = e0.elapsed_time(e1) / (args.steps * jobs)
+        unfused = {"value": round(1e3 / ums, 2), "unit": "ct-mults/s", "ms_per_mult": round(ums, 4),
+                   "path": "mul_k + relin_k + rescale_multi"}
+        log("unfused: %.3f ms per multiply, %.1f ct-mults/s" % (ums, 1e3 / ums))
 
     bytes_per_mult = mult_bytes(N, k, level, K, prm.alpha, jobs)
     cpu = None if args.no_cpu_baseline else cpu_baseline(log_n, L, K, dnum, k, level)

@@ -79,9 +79,9 @@ const char* mick_last_error(void);
 
 /* ---------------------------------------------------------------- params
  * Ring degree N = 2^log_n (13 <= log_n <= 16), L ciphertext primes
- * (1 <= L <= 60), K special primes (1 <= K <= 8), dnum digits with
- * alpha = ceil(L / dnum) <= 8 primes each and at most 16 digits (the 64-bit
- * sums of the basis conversions hold at most 8 products of 61 bits).
+ * (1 <= L <= 60), K special primes (1 <= K <= 24), dnum digits with
+ * alpha = ceil(L / dnum) <= 32 primes each and at most 16 digits.  dnum = 1
+ * with K >= L is the setting of the paper's evaluation (Sec. VI).
  * Builds the primes, NTT twiddle tables, basis conversion tables and
  * rescaling constants of Sec. II and Sec. V-B, and
  * uploads them to the current HIP device (synchronous).  The handle is

@@ -449,10 +449,10 @@ int mick_params_create(int log_n, int L, int K, int dnum, mick_params** out) {
   *out = nullptr;
   if (log_n < 13 || log_n > 16) return set_error(MICK_E_ARG, "log_n must be in 13..16");
   if (L < 1 || L > 60 || K < 1 || K > kMaxKp || dnum < 1 || dnum > L)
-    return set_error(MICK_E_ARG, "need 1 <= L <= 60, 1 <= K <= 8, 1 <= dnum <= L");
+    return set_error(MICK_E_ARG, "need 1 <= L <= 60, 1 <= K <= 24, 1 <= dnum <= L");
   const int alpha = (L + dnum - 1) / dnum;
   if (alpha > kMaxAlpha || (L + alpha - 1) / alpha > 16)
-    return set_error(MICK_E_ARG, "ceil(L / dnum) must be at most 8");
+    return set_error(MICK_E_ARG, "ceil(L / dnum) must be at most 32, with at most 16 digits");
   std::unique_ptr<mick_params> p(new mick_params());
   p->log_n = log_n;
   p->N = 1 << log_n;

@@ -352,8 +352,9 @@ void launch_pass(int logr, dim3 grid, hipStream_t s, const uint32_t* src, uint32
 // Workgroup order: the targets of one source tile run back to back on one
 // XCD (block b goes to XCD b % 8), so the source tile is read from L2.
 // The conversion constants carry a factor R = 2^32 (Montgomery form): the
-// sum of ALPHA <= 8 products of a residue below 2^30 and a constant below m
-// stays below 2m 2^32, so one Montgomery reduction returns it mod m.
+// sum of up to 8 products of a residue below 2^30 and a constant below m
+// stays below 2m 2^32, so one Montgomery reduction returns it mod m (wider
+// digits reduce every eight rows).
 template <int LOGR, int ALPHA, bool LAZY>
 __device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na, const uint32_t (&cc)[ALPHA],
                                              uint32_t minv, uint32_t* dst, uint32_t* lds, int H, int col0,
@@ -382,6 +383,11 @@ __device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na,
     uint32_t v[2][R1::E];
 #pragma unroll
     for (int j = 0; j < R1::E; j++) v[0][j] = __builtin_amdgcn_raw_buffer_load_b32(src, vj[j], 0, 0);
+    // more than eight rows: every eight rows' sum (below 2m 2^32) is reduced
+    // and the partial results are added mod q
+    uint32_t part[ALPHA > 8 ? R1::E : 1];
+#pragma unroll
+    for (int j = 0; j < (ALPHA > 8 ? R1::E : 1); j++) part[j] = 0;
 #pragma unroll
     for (int a = 0; a < ALPHA; a++) {
       if (a + 1 < ALPHA) {
@@ -392,10 +398,22 @@ __device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na,
       }
 #pragma unroll
       for (int j = 0; j < R1::E; j++) acc[j] += (uint64_t)v[a & 1][j] * cc[a];
+      if constexpr (ALPHA > 8) {
+        if ((a & 7) == 7 && a + 1 < ALPHA) {
+#pragma unroll
+          for (int j = 0; j < R1::E; j++) {
+            part[j] = add_mod(part[j], redc_2m(acc[j], q, minv), q);
+            acc[j] = 0;
+          }
+        }
+      }
     }
     uint32_t x[R1::E];
 #pragma unroll
-    for (int j = 0; j < R1::E; j++) x[j] = redc_2m(acc[j], q, minv);
+    for (int j = 0; j < R1::E; j++) {
+      x[j] = redc_2m(acc[j], q, minv);
+      if constexpr (ALPHA > 8) x[j] = add_mod(part[j], x[j], q);
+    }
     item_bfly<R1::RB, true, LAZY, false>(x, tw, R1::SL0, 0, hi, 0, q, nf);
     store_lds<R1, G::PAD>(x, lds, c, rb);
   }
@@ -856,7 +874,9 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
     case 1: MICK_MA(LR, 1); break;         \
     case 2: MICK_MA(LR, 2); break;         \
     case 4: MICK_MA(LR, 4); break;         \
-    default: MICK_MA(LR, 8); break;        \
+    case 8: MICK_MA(LR, 8); break;         \
+    case 16: MICK_MA(LR, 16); break;       \
+    default: MICK_MA(LR, 32); break;       \
   }
   if (la == 7) {
     MICK_MA_A(7)
@@ -916,12 +936,14 @@ int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blo
   ProfScope ps(P_MODUP, s);
   const DevTables& T = prm->dt;
 #define MICK_MA(LR, AL) k_modup_a_jt<LR, AL><<<blocks, kThreads, 0, s>>>(jt, nj, G, T)
-#define MICK_MA_A(LR)               \
-  switch (modup_rows(G.alpha)) {    \
-    case 1: MICK_MA(LR, 1); break;  \
-    case 2: MICK_MA(LR, 2); break;  \
-    case 4: MICK_MA(LR, 4); break;  \
-    default: MICK_MA(LR, 8); break; \
+#define MICK_MA_A(LR)                \
+  switch (modup_rows(G.alpha)) {     \
+    case 1: MICK_MA(LR, 1); break;   \
+    case 2: MICK_MA(LR, 2); break;   \
+    case 4: MICK_MA(LR, 4); break;   \
+    case 8: MICK_MA(LR, 8); break;   \
+    case 16: MICK_MA(LR, 16); break; \
+    default: MICK_MA(LR, 32); break; \
   }
   if (prm->split_a == 7) {
     MICK_MA_A(7)

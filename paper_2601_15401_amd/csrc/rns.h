@@ -4,13 +4,16 @@
 
 namespace mick {
 
-constexpr int kMaxAlpha = 8;  // primes per key-switching digit
-constexpr int kMaxKp = 8;     // special primes p_i
-constexpr int kMaxE = 68;     // extended basis: 60 ciphertext primes + 8 special primes
+constexpr int kMaxAlpha = 32;  // primes per key-switching digit
+constexpr int kMaxKp = 24;     // special primes p_i
 
-// Rows of the ModUp table for a digit width alpha: the kernels are built for
-// alpha in {1, 2, 4, 8} and read zero-padded rows up to that width.
-inline int modup_rows(int alpha) { return alpha <= 2 ? alpha : (alpha <= 4 ? 4 : 8); }
+// Rows of a digit's conversion table as the ModUp kernel reads them (the
+// digit width rounded up to a power of two; padded rows are zero).
+inline int modup_rows(int alpha) {
+  int r = 1;
+  while (r < alpha) r <<= 1;
+  return r;
+}
 
 struct CtPtrs {
   const uint32_t* p[kMaxK];

@@ -106,19 +106,21 @@ __global__ __launch_bounds__(kThreads) void k_tensor_jt(const JobDesc* jt, int j
 // uniform addresses): phat_i^-1 (+Shoup) [K][2], p_i^-1 mod q_j [K][level],
 // the chain's q_d^-1 mod q_t (+Shoup) [MU][MU][2], g^{mu,l-1}_eta (+Shoup)
 // [top][2] and g^{mu,t}_eta [top][MU].
-constexpr int kMdLdsWords = 2 * kMaxKp + kMaxKp * 60 + 2 * 12 * 12 + 2 * 60 + 60 * 12;
+// KP: special primes the kernel is built for (8 or 24; rows beyond K are zero).
+template <int KP>
+constexpr int md_lds_words() { return 2 * KP + KP * 60 + 2 * 12 * 12 + 2 * 60 + 60 * 12; }
 
-template <int MU>
+template <int MU, int KP>
 __device__ __forceinline__ void moddown_stage(const MdArgs& A, uint32_t* c) {
   const int top = A.level - MU;
   uint32_t* phinv = c;
-  uint32_t* pinvq = phinv + 2 * kMaxKp;
-  uint32_t* chain = pinvq + kMaxKp * 60;
+  uint32_t* pinvq = phinv + 2 * KP;
+  uint32_t* chain = pinvq + KP * 60;
   uint32_t* gtop = chain + 2 * 12 * 12;
   uint32_t* gt = gtop + 2 * 60;
   // rows i >= K are zero, so the loops over the special primes need no bounds
-  for (int i = threadIdx.x; i < 2 * kMaxKp; i += kThreads) phinv[i] = i < 2 * A.K ? A.md[i] : 0u;
-  for (int i = threadIdx.x; i < kMaxKp * A.level; i += kThreads) {
+  for (int i = threadIdx.x; i < 2 * KP; i += kThreads) phinv[i] = i < 2 * A.K ? A.md[i] : 0u;
+  for (int i = threadIdx.x; i < KP * A.level; i += kThreads) {
     const int pi = i / A.level, j = i - pi * A.level;
     pinvq[i] = pi < A.K ? A.md[2 * A.K + (size_t)pi * A.L + j] : 0u;
   }
@@ -137,31 +139,38 @@ __device__ __forceinline__ void moddown_stage(const MdArgs& A, uint32_t* c) {
   __syncthreads();
 }
 
-template <int MU>
+template <int MU, int KP>
 __device__ __forceinline__ void moddown_body(const uint32_t* acc, uint32_t* out, const MdArgs& A, int l, size_t n,
                                              const uint32_t* c, const DevTables& T) {
   const size_t N = (size_t)1 << A.log_n;
   const uint32_t* row = acc + (size_t)l * A.E * N + n;
   uint32_t* o = out + (size_t)l * (A.level - MU) * N + n;
   const uint32_t* phinv = c;
-  const uint32_t* pinvq = phinv + 2 * kMaxKp;
-  const uint32_t* chain = pinvq + kMaxKp * 60;
+  const uint32_t* pinvq = phinv + 2 * KP;
+  const uint32_t* chain = pinvq + KP * 60;
   const uint32_t* gtop = chain + 2 * 12 * 12;
   const uint32_t* gt = gtop + 2 * 60;
   // scaled p residues z_i = [phat_i^-1 x_i]_{p_i}; for i >= K the staged
   // constant is 0 (and the row read is the last special prime's)
-  uint32_t z[kMaxKp];
+  uint32_t z[KP];
 #pragma unroll
-  for (int i = 0; i < kMaxKp; i++) {
+  for (int i = 0; i < KP; i++) {
     const int ii = min(i, A.K - 1);
     z[i] = shoup(row[(size_t)(A.level + ii) * N], phinv[2 * i], phinv[2 * i + 1], T.mod[A.L + ii]);
   }
+  // each product z_i [p_i^-1]_{q_j} is below 2^61, so eight of them fit 64
+  // bits: wider special bases reduce every eight terms
   auto cstar = [&](int j, uint32_t x) -> uint32_t {
     const Red64 rc = T.red[j];
-    uint64_t s = 0;
+    uint32_t r = 0;
 #pragma unroll
-    for (int i = 0; i < kMaxKp; i++) s += (uint64_t)z[i] * pinvq[i * A.level + j];
-    return sub_mod(x, reduce64(s, rc), rc.m);
+    for (int i0 = 0; i0 < KP; i0 += 8) {
+      uint64_t s = 0;
+#pragma unroll
+      for (int i = i0; i < i0 + 8 && i < KP; i++) s += (uint64_t)z[i] * pinvq[i * A.level + j];
+      r = i0 == 0 ? reduce64(s, rc) : add_mod(r, reduce64(s, rc), rc.m);
+    }
+    return sub_mod(x, r, rc.m);
   };
   if constexpr (MU == 0) {
     for (int j = 0; j < A.level; j++) o[(size_t)j * N] = cstar(j, row[(size_t)j * N]);
@@ -216,17 +225,17 @@ __device__ __forceinline__ void moddown_body(const uint32_t* acc, uint32_t* out,
   }
 }
 
-template <int MU>
+template <int MU, int KP>
 __global__ __launch_bounds__(kThreads) void k_moddown_rs(const uint32_t* acc, uint32_t* out, MdArgs A, DevTables T) {
-  __shared__ uint32_t c[kMdLdsWords];
-  moddown_stage<MU>(A, c);
+  __shared__ uint32_t c[md_lds_words<KP>()];
+  moddown_stage<MU, KP>(A, c);
   const size_t job = blockIdx.z;
-  moddown_body<MU>(acc + job * (size_t)A.acc_job, out + job * (size_t)A.out_job, A, blockIdx.y,
+  moddown_body<MU, KP>(acc + job * (size_t)A.acc_job, out + job * (size_t)A.out_job, A, blockIdx.y,
                    (size_t)blockIdx.x * kThreads + threadIdx.x, c, T);
 }
 
 // Job-table form: jobs [j0, j0 + nj) of equal k = MU + 1; blocks per job 2 N / 256.
-template <int MU>
+template <int MU, int KP>
 __global__ __launch_bounds__(kThreads) void k_moddown_rs_jt(const JobDesc* jt, int j0, int nj, GroupConsts G,
                                                             DevTables T) {
   const int j = j0 + find_job(jt + j0, nj, S_MODDOWN, blockIdx.x);
@@ -244,9 +253,9 @@ __global__ __launch_bounds__(kThreads) void k_moddown_rs_jt(const JobDesc* jt, i
   A.K = G.K;
   A.E = level + G.K;
   const WsLayout lay(MU + 1, level, G.K, G.alpha, G.log_n);
-  __shared__ uint32_t c[kMdLdsWords];
-  moddown_stage<MU>(A, c);
-  moddown_body<MU>(jt[j].ws + lay.acc, jt[j].out, A, local / xb, (size_t)(local % xb) * kThreads + threadIdx.x, c,
+  __shared__ uint32_t c[md_lds_words<KP>()];
+  moddown_stage<MU, KP>(A, c);
+  moddown_body<MU, KP>(jt[j].ws + lay.acc, jt[j].out, A, local / xb, (size_t)(local % xb) * kThreads + threadIdx.x, c,
                    T);
 }
 
@@ -405,9 +414,15 @@ int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out
   dim3 grid((unsigned)(prm->N / kThreads), 2, (unsigned)n_jobs);
   const DevTables& T = prm->dt;
   ProfScope ps(P_MODDOWN_RS, s);
+  const bool wide = A.K > 8;
   switch (mu) {
-#define MICK_M(MM) \
-  case MM: k_moddown_rs<MM><<<grid, kThreads, 0, s>>>(acc, out, A, T); break;
+#define MICK_M(MM)                                                          \
+  case MM:                                                                  \
+    if (wide)                                                               \
+      k_moddown_rs<MM, 24><<<grid, kThreads, 0, s>>>(acc, out, A, T);       \
+    else                                                                    \
+      k_moddown_rs<MM, 8><<<grid, kThreads, 0, s>>>(acc, out, A, T);        \
+    break;
     MICK_M(0) MICK_M(1) MICK_M(2) MICK_M(3) MICK_M(4) MICK_M(5) MICK_M(6) MICK_M(7) MICK_M(8) MICK_M(9) MICK_M(10)
     MICK_M(11)
 #undef MICK_M
@@ -436,9 +451,15 @@ int launch_moddown_rs_jt(const mick_params* prm, const JobDesc* jt, int j0, int 
   if (blocks <= 0) return MICK_OK;
   const DevTables& T = prm->dt;
   ProfScope ps(P_MODDOWN_RS, s);
+  const bool wide = G.K > 8;
   switch (mu) {
-#define MICK_M(MM) \
-  case MM: k_moddown_rs_jt<MM><<<blocks, kThreads, 0, s>>>(jt, j0, nj, G, T); break;
+#define MICK_M(MM)                                                               \
+  case MM:                                                                       \
+    if (wide)                                                                    \
+      k_moddown_rs_jt<MM, 24><<<blocks, kThreads, 0, s>>>(jt, j0, nj, G, T);     \
+    else                                                                         \
+      k_moddown_rs_jt<MM, 8><<<blocks, kThreads, 0, s>>>(jt, j0, nj, G, T);      \
+    break;
     MICK_M(1) MICK_M(2) MICK_M(3) MICK_M(4) MICK_M(5) MICK_M(6) MICK_M(7) MICK_M(8) MICK_M(9) MICK_M(10) MICK_M(11)
 #undef MICK_M
     default: return set_error(MICK_E_ARG, "mu out of range for the fused rescale");

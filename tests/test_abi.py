@@ -37,8 +37,9 @@ def test_status_strings_without_gpu():
     # argument validation happens before any device work
     out = ctypes.c_void_p()
     assert lib.mick_params_create(12, 3, 1, 3, ctypes.byref(out)) == -1
-    assert lib.mick_params_create(13, 3, 9, 3, ctypes.byref(out)) == -1
-    assert lib.mick_params_create(16, 32, 8, 2, ctypes.byref(out)) == -1
+    assert lib.mick_params_create(13, 3, 25, 3, ctypes.byref(out)) == -1   # K > 24
+    assert lib.mick_params_create(16, 40, 8, 1, ctypes.byref(out)) == -1   # digit of 40 primes
+    assert lib.mick_params_create(16, 34, 8, 34, ctypes.byref(out)) == -1  # 34 digits
 
 
 def test_queue_schedule_allocator_validate_without_gpu():
