@@ -333,7 +333,6 @@ def run_mixed(args, torch, mick):
                    "parallelism": "none"},
         "plain": plain,
         "batched_over_plain": round(value / plain["value"], 3) if plain else None,
-        **({"unfused": unfused} if unfused else {}),
         "queue": {"value": round(n_jobs / (q_ms / 1e3), 2), "unit": "ct-mults/s", "ms_per_512_wall": round(q_ms, 3)},
         "schedules": schedules,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
@@ -750,6 +749,7 @@ def main():
                    "k": k, "log_n": log_n, "level": level, "batch": jobs, "parallelism": "none"},
         "plain": plain,
         "batched_over_plain": round(value / plain["value"], 3) if plain else None,
+        **({"unfused": unfused} if unfused else {}),
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4), "of": "one batched step"},
         "hbm_frac_whole_path": round(value * bytes_per_mult / 1e9 / HBM_PEAK_GBS, 5),

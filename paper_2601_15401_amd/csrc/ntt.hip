@@ -498,8 +498,11 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   const size_t N = (size_t)1 << A.log_n;
   const int s0 = A.log_n - LOGR;
   const uint4 nf{};
-  // every (t, b) pair of this tile uses the same twiddles: stage them once
-  for (int i = threadIdx.x; i < G::COLS * ((1 << LOGR) - 1); i += kKipThreads) {
+  // every (t, b) pair of this tile uses the same twiddles: stage them once.
+  // A limb of the only digit (B = 1, e < level) is its own ModUp image in
+  // every pair, so it transforms nothing and skips the staging.
+  const bool transforms = A.B > 1 || e >= A.level;
+  for (int i = threadIdx.x; transforms && i < G::COLS * ((1 << LOGR) - 1); i += kKipThreads) {
     const int c = i & (G::COLS - 1);
     const int k = i >> G::LOGC;  // (2^sl - 1) + rr
     const int sl = 31 - __clz(k + 1);
@@ -876,7 +879,9 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
     case 4: MICK_MA(LR, 4); break;         \
     case 8: MICK_MA(LR, 8); break;         \
     case 16: MICK_MA(LR, 16); break;       \
-    default: MICK_MA(LR, 32); break;       \
+    case 24: MICK_MA(LR, 24); break;       \
+    case 32: MICK_MA(LR, 32); break;       \
+    default: return set_error(MICK_E_ARG, "digit width out of range"); \
   }
   if (la == 7) {
     MICK_MA_A(7)
@@ -943,7 +948,9 @@ int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blo
     case 4: MICK_MA(LR, 4); break;   \
     case 8: MICK_MA(LR, 8); break;   \
     case 16: MICK_MA(LR, 16); break; \
-    default: MICK_MA(LR, 32); break; \
+    case 24: MICK_MA(LR, 24); break; \
+    case 32: MICK_MA(LR, 32); break; \
+    default: return set_error(MICK_E_ARG, "digit width out of range"); \
   }
   if (prm->split_a == 7) {
     MICK_MA_A(7)

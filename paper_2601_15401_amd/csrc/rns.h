@@ -7,9 +7,10 @@ namespace mick {
 constexpr int kMaxAlpha = 32;  // primes per key-switching digit
 constexpr int kMaxKp = 24;     // special primes p_i
 
-// Rows of a digit's conversion table as the ModUp kernel reads them (the
-// digit width rounded up to a power of two; padded rows are zero).
+// Rows of a digit's conversion table as the ModUp kernel reads them: the
+// digit width rounded up to 1, 2, 4, 8, 16, 24 or 32 (padded rows are zero).
 inline int modup_rows(int alpha) {
+  if (alpha > 8) return (alpha + 7) / 8 * 8;
   int r = 1;
   while (r < alpha) r <<= 1;
   return r;

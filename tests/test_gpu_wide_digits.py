@@ -2,9 +2,9 @@
 single-digit setting of the paper's evaluation (dnum = 1, K >= L; Sec. VI,
 L = K = 24) and its neighbours, against the oracle, bit for bit.
 
-The digit widths cover the ModUp kernel's wide instantiations: 16 (exact),
-20 (padded to 32 rows, last chunk ragged), 24 (padded to 32) and 12 (two
-digits, padded to 16); K = 12..24 runs the 24-prime ModDown kernel.
+The digit widths cover the ModUp kernel's wide instantiations: 16 and 24
+(exact), 20 (padded to 24 rows, last chunk ragged) and 12 (two digits,
+padded to 16); K = 12..24 runs the 24-prime ModDown kernel.
 """
 import zlib
 
