@@ -202,6 +202,18 @@ struct TwGlobal {
   __device__ uint2 operator()(int s, int, int rr) const { return tw[(1 << s) + (rr << s0) + blk]; }
 };
 
+// Pass A's twiddles do not depend on the column: a tile uses tw[1 .. 2^LOGR)
+// of its prime, staged in LDS once per block.
+struct TwPassA {
+  const uint2* t;
+  __device__ uint2 operator()(int s, int, int rr) const { return t[(1 << s) + rr]; }
+};
+
+template <int LOGR>
+__device__ __forceinline__ void stage_tw_pass_a(uint2* ltwa, const uint2* tw) {
+  for (int i = threadIdx.x; i < (1 << LOGR); i += kThreads) ltwa[i] = tw[i];
+}
+
 template <int RB, bool FWD, bool LAZY, bool HAS_STAGE0>
 __device__ __forceinline__ void item_bfly(uint32_t (&x)[1 << RB], const uint2* tw, int s_first, int s0, int hi,
                                           int blk, uint32_t q, const uint4& nfix) {
@@ -275,14 +287,19 @@ __device__ __forceinline__ void store_lds(const uint32_t (&x)[RD::E], uint32_t* 
 
 // ------------------------------------------------------------------ plain transform pass
 
+// ltwa: LDS for pass A's twiddles, used by the forward pass A, whose second
+// round reads per-thread twiddles after the barrier (the first round's are
+// uniform per wave).
 template <int LOGR, bool FWD, bool LAZY, bool PASSB>
-__device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, uint32_t* lds, int s0, int H, int col0,
-                                          uint32_t q, const uint2* tw, const uint4& nfix) {
+__device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, uint32_t* lds, uint2* ltwa, int s0,
+                                          int H, int col0, uint32_t q, const uint2* tw, const uint4& nfix) {
   using G = Geo<LOGR>;
   // forward: strided round first; inverse: consecutive round first
   using R1 = Rnd<LOGR, PASSB, FWD>;
   using R2 = Rnd<LOGR, PASSB, !FWD>;
   constexpr bool FINAL = FWD ? PASSB : !PASSB;  // last pass of the transform
+  constexpr bool STAGED = FWD && !PASSB;
+  if constexpr (STAGED) stage_tw_pass_a<LOGR>(ltwa, tw);
 #pragma unroll
   for (int i = 0; i < R1::NI; i++) {
     int c, rb, hi;
@@ -300,7 +317,10 @@ __device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, ui
     uint32_t x[R2::E];
     load_lds<R2, G::PAD>(x, lds, c, rb);
     // the inverse's strided round of pass A holds global stage 0
-    item_bfly<R2::RB, FWD, LAZY, !FWD && !PASSB>(x, tw, s0 + R2::SL0, s0, hi, PASSB ? col0 + c : 0, q, nfix);
+    if constexpr (STAGED)
+      item_bfly_t<R2::RB, FWD, LAZY, false>(x, TwPassA{ltwa}, R2::SL0, hi, q, nfix);
+    else
+      item_bfly<R2::RB, FWD, LAZY, !FWD && !PASSB>(x, tw, s0 + R2::SL0, s0, hi, PASSB ? col0 + c : 0, q, nfix);
     if constexpr (FINAL) {
 #pragma unroll
       for (int j = 0; j < R2::E; j++) x[j] = canonical<FWD, LAZY>(x[j], q);
@@ -321,6 +341,7 @@ template <int LOGR, bool FWD, bool PASSB>
 __global__ __launch_bounds__(kThreads) void k_ntt_pass(const uint32_t* src, uint32_t* dst, LimbMap mp, DevTables T,
                                                        int log_n, int s0) {
   __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  __shared__ uint2 ltwa[FWD && !PASSB ? 1 << LOGR : 1];
   int prime, pos;
   size_t off;
   resolve(mp, blockIdx.y, log_n, prime, pos, off);
@@ -331,9 +352,9 @@ __global__ __launch_bounds__(kThreads) void k_ntt_pass(const uint32_t* src, uint
   const int H = log_n - s0 - LOGR;  // > 0 in pass A, 0 in pass B
   const int col0 = blockIdx.x * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    pass_body<LOGR, FWD, true, PASSB>(src + off, dst + off, lds, s0, H, col0, q, tw, nfix);
+    pass_body<LOGR, FWD, true, PASSB>(src + off, dst + off, lds, ltwa, s0, H, col0, q, tw, nfix);
   else
-    pass_body<LOGR, FWD, false, PASSB>(src + off, dst + off, lds, s0, H, col0, q, tw, nfix);
+    pass_body<LOGR, FWD, false, PASSB>(src + off, dst + off, lds, ltwa, s0, H, col0, q, tw, nfix);
 }
 
 template <bool FWD, bool PASSB>
@@ -357,12 +378,14 @@ void launch_pass(int logr, dim3 grid, hipStream_t s, const uint32_t* src, uint32
 // digits reduce every eight rows).
 template <int LOGR, int ALPHA, bool LAZY>
 __device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na, const uint32_t (&cc)[ALPHA],
-                                             uint32_t minv, uint32_t* dst, uint32_t* lds, int H, int col0,
-                                             uint32_t q, const uint2* tw) {
+                                             uint32_t minv, uint32_t* dst, uint32_t* lds, uint2* ltwa, int H,
+                                             int col0, uint32_t q, const uint2* tw) {
   using G = Geo<LOGR>;
   using R1 = Rnd<LOGR, false, true>;
   using R2 = Rnd<LOGR, false, false>;
   const uint4 nf{};
+  // the second round's twiddles vary per thread: read from LDS after the barrier
+  stage_tw_pass_a<LOGR>(ltwa, tw);
   // the item's rows are 2^NLO_LOG rows apart: a uniform byte step per j
   constexpr uint32_t kRowStep = 4u << R1::NLO_LOG;
   const uint32_t row_bytes = 4u << (H + LOGR);  // one source limb
@@ -424,7 +447,7 @@ __device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na,
     R2::decode(i * kThreads + threadIdx.x, c, rb, hi);
     uint32_t x[R2::E];
     load_lds<R2, G::PAD>(x, lds, c, rb);
-    item_bfly<R2::RB, true, LAZY, false>(x, tw, R2::SL0, 0, hi, 0, q, nf);
+    item_bfly_t<R2::RB, true, LAZY, false>(x, TwPassA{ltwa}, R2::SL0, hi, q, nf);
     store_global<R2>(x, dst, H, col0 + c, rb);
   }
 }
@@ -438,6 +461,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, 
 template <int LOGR, int ALPHA>
 __global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint32_t* X, ModupArgs A, DevTables T) {
   __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  __shared__ uint2 ltwa[1 << LOGR];
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
   const int e = seq % A.E;
   const int unit = (seq / A.E) * 8 + xcd;  // (job, t, b, tile)
@@ -465,9 +489,9 @@ __global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint3
   const int H = A.log_n - LOGR;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    modup_a_body<LOGR, ALPHA, true>(src, na, cc, minv, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, true>(src, na, cc, minv, dst, lds, ltwa, H, col0, q, tw);
   else
-    modup_a_body<LOGR, ALPHA, false>(src, na, cc, minv, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, false>(src, na, cc, minv, dst, lds, ltwa, H, col0, q, tw);
 }
 
 // ------------------------------------------------------------------ pass B + key inner product
@@ -691,6 +715,7 @@ template <int LOGR, bool FWD, bool PASSB>
 __global__ __launch_bounds__(kThreads) void k_ntt_pass_jt(const JobDesc* jt, int nj, int stage, GroupConsts G,
                                                           DevTables T, int s0) {
   __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  __shared__ uint2 ltwa[FWD && !PASSB ? 1 << LOGR : 1];
   constexpr bool FIRST = FWD ? !PASSB : PASSB;  // the transform's first pass reads the source
   const int j = find_job(jt, nj, stage, blockIdx.x);
   const int local = blockIdx.x - jt[j].blk0[stage];
@@ -734,9 +759,9 @@ __global__ __launch_bounds__(kThreads) void k_ntt_pass_jt(const JobDesc* jt, int
   const int H = log_n - s0 - LOGR;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    pass_body<LOGR, FWD, true, PASSB>(src, dst, lds, s0, H, col0, q, tw, nfix);
+    pass_body<LOGR, FWD, true, PASSB>(src, dst, lds, ltwa, s0, H, col0, q, tw, nfix);
   else
-    pass_body<LOGR, FWD, false, PASSB>(src, dst, lds, s0, H, col0, q, tw, nfix);
+    pass_body<LOGR, FWD, false, PASSB>(src, dst, lds, ltwa, s0, H, col0, q, tw, nfix);
 }
 
 // ModUp conversion + pass A over the jobs of a table.  Blocks per job:
@@ -745,6 +770,7 @@ __global__ __launch_bounds__(kThreads) void k_ntt_pass_jt(const JobDesc* jt, int
 template <int LOGR, int ALPHA>
 __global__ __launch_bounds__(kThreads) void k_modup_a_jt(const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
   __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+  __shared__ uint2 ltwa[1 << LOGR];
   const int j = find_job(jt, nj, S_MODUP, blockIdx.x);
   const int local = blockIdx.x - jt[j].blk0[S_MODUP];
   const int log_n = G.log_n;
@@ -777,9 +803,9 @@ __global__ __launch_bounds__(kThreads) void k_modup_a_jt(const JobDesc* jt, int 
   const int H = log_n - LOGR;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    modup_a_body<LOGR, ALPHA, true>(src, na, cc, minv, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, true>(src, na, cc, minv, dst, lds, ltwa, H, col0, q, tw);
   else
-    modup_a_body<LOGR, ALPHA, false>(src, na, cc, minv, dst, lds, H, col0, q, tw);
+    modup_a_body<LOGR, ALPHA, false>(src, na, cc, minv, dst, lds, ltwa, H, col0, q, tw);
 }
 
 // Pass B + key inner product over the jobs of a table.  Blocks per job:
