@@ -525,13 +525,29 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   // every (t, b) pair of this tile uses the same twiddles: stage them once.
   // A limb of the only digit (B = 1, e < level) is its own ModUp image in
   // every pair, so it transforms nothing and skips the staging.
+  // All loads are issued before the first LDS write, so the staging costs
+  // one memory latency, not one per iteration.
   const bool transforms = A.B > 1 || e >= A.level;
-  for (int i = threadIdx.x; transforms && i < G::COLS * ((1 << LOGR) - 1); i += kKipThreads) {
-    const int c = i & (G::COLS - 1);
-    const int k = i >> G::LOGC;  // (2^sl - 1) + rr
-    const int sl = 31 - __clz(k + 1);
-    const int rr = k + 1 - (1 << sl);
-    ltw[i] = tw[(1 << (s0 + sl)) + (rr << s0) + col0 + c];
+  if (transforms) {
+    constexpr int NTW = G::COLS * ((1 << LOGR) - 1);
+    constexpr int IT = (NTW + kKipThreads - 1) / kKipThreads;
+    uint2 t[IT];
+#pragma unroll
+    for (int it = 0; it < IT; it++) {
+      const int i = it * kKipThreads + threadIdx.x;
+      if (i < NTW) {
+        const int c = i & (G::COLS - 1);
+        const int k = i >> G::LOGC;  // (2^sl - 1) + rr
+        const int sl = 31 - __clz(k + 1);
+        const int rr = k + 1 - (1 << sl);
+        t[it] = tw[(1 << (s0 + sl)) + (rr << s0) + col0 + c];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; it++) {
+      const int i = it * kKipThreads + threadIdx.x;
+      if (i < NTW) ltw[i] = t[it];
+    }
   }
   // pairs p = (t - 2) B + b.  A pair is "own" when limb e belongs to digit b:
   // its ModUp image is D_t itself (NTT domain, round-2 layout); otherwise the

@@ -110,8 +110,30 @@ __global__ __launch_bounds__(kThreads) void k_tensor_jt(const JobDesc* jt, int j
 template <int KP>
 constexpr int md_lds_words() { return 2 * KP + KP * 60 + 2 * 12 * 12 + 2 * 60 + 60 * 12; }
 
+// Loads up to IT x kThreads words: v[it] = get(i) for i = it kThreads + tid < n.
+template <int IT, typename Get>
+__device__ __forceinline__ void gather_words(uint32_t (&v)[IT], int n, Get get) {
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int i = it * kThreads + threadIdx.x;
+    if (i < n) v[it] = get(i);
+  }
+}
+
+template <int IT>
+__device__ __forceinline__ void put_words(const uint32_t (&v)[IT], int n, uint32_t* dst) {
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int i = it * kThreads + threadIdx.x;
+    if (i < n) dst[i] = v[it];
+  }
+}
+
+// Stages the ModDown and rescale constants in LDS.  Every load is issued
+// before the first LDS store, so staging costs one memory latency.
 template <int MU, int KP>
 __device__ __forceinline__ void moddown_stage(const MdArgs& A, uint32_t* c) {
+  constexpr int M1 = MU > 0 ? MU : 1;
   const int top = A.level - MU;
   uint32_t* phinv = c;
   uint32_t* pinvq = phinv + 2 * KP;
@@ -119,22 +141,32 @@ __device__ __forceinline__ void moddown_stage(const MdArgs& A, uint32_t* c) {
   uint32_t* gtop = chain + 2 * 12 * 12;
   uint32_t* gt = gtop + 2 * 60;
   // rows i >= K are zero, so the loops over the special primes need no bounds
-  for (int i = threadIdx.x; i < 2 * KP; i += kThreads) phinv[i] = i < 2 * A.K ? A.md[i] : 0u;
-  for (int i = threadIdx.x; i < KP * A.level; i += kThreads) {
+  uint32_t vph[1], vpi[(KP * 60 + kThreads - 1) / kThreads], vch[2], vgtop[1], vgt[(60 * M1 + kThreads - 1) / kThreads];
+  gather_words(vph, 2 * KP, [&](int i) { return i < 2 * A.K ? A.md[i] : 0u; });
+  gather_words(vpi, KP * A.level, [&](int i) {
     const int pi = i / A.level, j = i - pi * A.level;
-    pinvq[i] = pi < A.K ? A.md[2 * A.K + (size_t)pi * A.L + j] : 0u;
-  }
+    return pi < A.K ? A.md[2 * A.K + (size_t)pi * A.L + j] : 0u;
+  });
+  // chain: rescale u drops q_{l-u}; entry (u, t) is q_{l-u}^-1 mod q_{top+t}
+  // (+Shoup), for u >= 1 and t < MU - u
+  auto chain_src = [&](int i) -> const uint32_t* {
+    const int u = i / M1, t = i - u * M1;
+    return (u >= 1 && t < MU - u) ? A.qinvq + 2 * ((size_t)(A.level - u) * A.L + top + t) : nullptr;
+  };
   if constexpr (MU > 0) {
-    for (int i = threadIdx.x; i < MU * MU; i += kThreads) {
-      const int u = i / MU, t = i - u * MU;  // rescale u drops q_{l-u}; limb top + t
-      if (u >= 1 && t < MU - u) {
-        const uint32_t* ci = A.qinvq + 2 * ((size_t)(A.level - u) * A.L + top + t);
-        chain[2 * i] = ci[0];
-        chain[2 * i + 1] = ci[1];
-      }
-    }
-    for (int i = threadIdx.x; i < 2 * top; i += kThreads) gtop[i] = A.rs[i];
-    for (int i = threadIdx.x; i < top * MU; i += kThreads) gt[i] = A.rs[2 * top + i];
+    gather_words(vch, 2 * MU * MU, [&](int i) {
+      const uint32_t* ci = chain_src(i >> 1);
+      return ci ? ci[i & 1] : 0u;
+    });
+    gather_words(vgtop, 2 * top, [&](int i) { return A.rs[i]; });
+    gather_words(vgt, top * MU, [&](int i) { return A.rs[2 * top + i]; });
+  }
+  put_words(vph, 2 * KP, phinv);
+  put_words(vpi, KP * A.level, pinvq);
+  if constexpr (MU > 0) {
+    put_words(vch, 2 * MU * MU, chain);
+    put_words(vgtop, 2 * top, gtop);
+    put_words(vgt, top * MU, gt);
   }
   __syncthreads();
 }
@@ -269,15 +301,14 @@ __global__ __launch_bounds__(kThreads) void k_rs_sums(const uint32_t* topc, uint
   __shared__ uint32_t gt[60 * MU];         // [top <= 60][MU]
   {
     const int top = A.level - MU;
-    for (int i = threadIdx.x; i < MU * MU; i += kThreads) {
-      const int u = i / MU, t = i - u * MU;
-      if (u >= 1 && t < MU - u) {
-        const uint32_t* ci = A.qinvq + 2 * ((size_t)(A.level - u) * A.L + top + t);
-        chain[2 * i] = ci[0];
-        chain[2 * i + 1] = ci[1];
-      }
-    }
-    for (int i = threadIdx.x; i < top * MU; i += kThreads) gt[i] = A.rs[2 * top + i];
+    uint32_t vch[2], vgt[(60 * MU + kThreads - 1) / kThreads];
+    gather_words(vch, 2 * MU * MU, [&](int i) {
+      const int u = (i >> 1) / MU, t = (i >> 1) - u * MU;
+      return (u >= 1 && t < MU - u) ? A.qinvq[2 * ((size_t)(A.level - u) * A.L + top + t) + (i & 1)] : 0u;
+    });
+    gather_words(vgt, top * MU, [&](int i) { return A.rs[2 * top + i]; });
+    put_words(vch, 2 * MU * MU, chain);
+    put_words(vgt, top * MU, gt);
     __syncthreads();
   }
   const size_t N = (size_t)1 << A.log_n;
