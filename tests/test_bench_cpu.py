@@ -1,0 +1,59 @@
+"""bench.py's host logic: the one-GPU contract and the roofline object."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def _quiet(monkeypatch):
+    monkeypatch.setattr(bench, "log", lambda *a: None)
+
+
+def test_roofline_ranks_each_transform_pass_as_its_own_kernel(monkeypatch):
+    _quiet(monkeypatch)
+    # both passes of the accumulators' INTT together take longer than the key
+    # products, but neither pass alone does
+    prof = {"passB_kip": (4.1, 20), "intt_acc.passA": (2.0, 20), "intt_acc.passB": (2.5, 20),
+            "tensor": (1.7, 20)}
+    rl = bench.roofline(prof, 20, 1 << 16, 3, 24, 24, 24, 8)
+    assert rl["kernel"] == "passB_kip"
+    assert rl["avg_launch_us"] == 205.0
+    b, _ = bench.site_work("passB_kip", 1 << 16, 3, 24, 24, 24, 8)
+    assert rl["algorithmic_bytes_per_launch"] == b
+    assert abs(rl["achieved"] - b / 205e-6 / 1e9) < 0.1
+
+
+def test_roofline_bound_is_the_larger_fraction(monkeypatch):
+    _quiet(monkeypatch)
+    N, k, level, K, alpha, jobs = 1 << 16, 8, 32, 8, 8, 8
+    rl = bench.roofline({"modup_bconv_passA": (25.4, 20)}, 20, N, k, level, K, alpha, jobs)
+    b, ops = bench.site_work("modup_bconv_passA", N, k, level, K, alpha, jobs)
+    tops = ops / 1.27e-3 / 1e12
+    assert rl["bound"] == "alu" and rl["unit"] == "TOP/s"
+    assert abs(rl["achieved"] - round(tops, 3)) < 1e-3
+    assert abs(rl["frac"] - tops / bench.ALU_PEAK_TOPS) < 1e-3
+    # a transform pass moves every limb once each way: HBM-bound
+    rl = bench.roofline({"intt_d.passB": (6.4, 20)}, 20, N, k, level, K, alpha, jobs)
+    assert rl["bound"] == "hbm" and rl["unit"] == "GB/s" and rl["peak"] == bench.HBM_PEAK_GBS
+
+
+def test_transform_pass_work_is_half_the_transform(monkeypatch):
+    _quiet(monkeypatch)
+    N, k, level, K, alpha, jobs = 1 << 16, 8, 32, 8, 8, 8
+    b, ops = bench.site_work("intt_d", N, k, level, K, alpha, jobs)
+    n = jobs * (k - 1) * level
+    assert b == 2 * 4.0 * N * n
+    assert ops == n * (N / 2) * 16 * 9.0  # 16 stages of N/2 butterflies
+    rl = bench.roofline({"intt_d.passA": (5.0, 20)}, 20, N, k, level, K, alpha, jobs)
+    assert abs(rl["alu_frac"] - (ops / 2) / 250e-6 / 1e12 / bench.ALU_PEAK_TOPS) < 1e-3
