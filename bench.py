@@ -76,11 +76,12 @@ def site_work(site, N, k, level, K, alpha, jobs):
         return limb * (n_in + n_out), jobs * new_limbs * (N * (2 * alpha + 12.0) + (N / 2) * stages_a * bfly)
     if site == "passB_kip":
         # reads pass-A outputs, the digits' own d_t, d_0 and d_1, the keys once per
-        # batch; writes the two accumulators
+        # batch; writes the two accumulators after the first pass of their INTT
         x = jobs * (new_limbs + (k - 1) * level)
         keys = (k - 1) * B * 2 * E
         return limb * (x + keys + jobs * 2 * level + jobs * 2 * E), \
-            jobs * (new_limbs * (N / 2) * stages_b * bfly + (k - 1) * B * E * N * 2 * 2.0 + 2 * E * N * 30.0)
+            jobs * ((new_limbs + 2 * E) * (N / 2) * stages_b * bfly + (k - 1) * B * E * N * 2 * 2.0
+                    + 2 * E * N * 30.0)
     if site.startswith("intt_d"):
         n = jobs * (k - 1) * level
         return 2 * limb * n, n * (N / 2) * log_n * bfly

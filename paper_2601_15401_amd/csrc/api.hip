@@ -394,12 +394,13 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
   ka.key_poly = (long long)(L + K) * N;
   ka.d_job = ka.x_job = ka.acc_job = (long long)job_stride;
   MICK_TRY(launch_kip_b(prm, ws + lay.X, ws + lay.D, keys->d_evk, ws + lay.acc, ka, s));
-  // relocated ModDown: INTT of every accumulator limb
+  // relocated ModDown: INTT of every accumulator limb (its first pass ran in
+  // the key-product kernel)
   LimbMap ma2 = simple_map(prm, 0, E);
   ma2.split = level;
   ma2.off_hi = L - level;
   ma2.job_stride = (long long)job_stride;
-  MICK_TRY(ntt_launch(prm, ws + lay.acc, ws + lay.acc, ma2, 2 * E, n_jobs, true, s, P_INTT_ACC));
+  MICK_TRY(intt_pass_a_launch(prm, ws + lay.acc, ma2, 2 * E, n_jobs, s, P_INTT_ACC));
   // scaled BConv, subtraction and the combined rescale, then the final NTT
   MdArgs A = md_args(prm, level, mu);
   A.acc_job = (long long)job_stride;

@@ -218,6 +218,10 @@ int hip_error(hipError_t e, const char* what);
 // Transforms (ntt.hip).  src may equal dst.
 int ntt_launch(const mick_params* prm, const uint32_t* src, uint32_t* dst, const LimbMap& map, int n_limbs, int n_jobs,
                bool inverse, hipStream_t s, int site = P_OTHER);
+// The inverse transform's second pass (pass A, with N^-1) alone, in place:
+// for limbs whose first pass (pass B) already ran elsewhere.
+int intt_pass_a_launch(const mick_params* prm, uint32_t* buf, const LimbMap& map, int n_limbs, int n_jobs,
+                       hipStream_t s, int site);
 LimbMap simple_map(const mick_params* prm, int first_prime, int n_limbs);
 
 inline size_t evk_offset(const mick_params* prm, int t, int b, int l) {

@@ -39,7 +39,10 @@
 //    product: one workgroup owns one tile of one extended-basis limb and
 //    accumulates sum_t sum_b X_{t,b} ek'_{t,b,l} over every (t, b) pair in
 //    registers, reusing the limb's pass-B twiddles for all pairs; the
-//    transformed limbs are never written.
+//    transformed limbs are never written.  The finished accumulator tile is
+//    already in the inverse transform's first-round layout, so the first
+//    pass (pass B) of the accumulators' INTT (Sec. IV relocated ModDown)
+//    runs in the same kernel and only its output is written.
 #include "internal.h"
 #include "rns.h"
 
@@ -513,7 +516,8 @@ struct TwLds {
 template <int LOGR, bool LAZY>
 __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* De, const uint32_t* evk_e,
                                            uint32_t* acc_e, const KipArgs& A, uint32_t* lds, uint2* ltw, int e,
-                                           int col0, uint32_t q, uint32_t minv, const Red64& red, const uint2* tw) {
+                                           int col0, uint32_t q, uint32_t minv, const Red64& red, const uint2* tw,
+                                           const uint2* itw) {
   using G = Geo<LOGR>;
   using R1 = Rnd<LOGR, true, true, kKipThreads>;
   using R2 = Rnd<LOGR, true, false, kKipThreads>;
@@ -669,6 +673,11 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
     const uint32_t th = shoup(shoup(hi, r32, r32sh, q), r32, r32sh, q);  // hi 2^64 mod q
     return mont_mul(add_mod(reduce64(lo, red), th, q), 1u, q, minv);
   };
+  // The finished tile is in the layout of the inverse transform's first
+  // round (pass B's consecutive round), so the first pass of the
+  // accumulators' INTT runs here: that round in registers, the strided round
+  // through the two LDS tiles, and the pass's output is what is written.
+  uint32_t y0[R2::NI][R2::E], y1[R2::NI][R2::E];
 #pragma unroll
   for (int i = 0; i < R2::NI; i++) {
     int c, rb, hi;
@@ -689,8 +698,34 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
         o1[j] = add_mod(o1[j], d1[j], q);
       }
     }
-    store_global<R2>(o0, acc_e, 0, col0 + c, rb);
-    store_global<R2>(o1, acc_e + (size_t)A.E * N, 0, col0 + c, rb);
+    item_bfly<R2::RB, false, LAZY, false>(o0, itw, s0 + R2::SL0, s0, hi, col0 + c, q, nf);
+    item_bfly<R2::RB, false, LAZY, false>(o1, itw, s0 + R2::SL0, s0, hi, col0 + c, q, nf);
+#pragma unroll
+    for (int j = 0; j < R2::E; j++) {
+      y0[i][j] = o0[j];
+      y1[i][j] = o1[j];
+    }
+  }
+  __syncthreads();  // every thread is done with the pair loop's tiles
+#pragma unroll
+  for (int i = 0; i < R2::NI; i++) {
+    int c, rb, hi;
+    R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+    store_lds<R2, G::PAD>(y0[i], lds, c, rb);
+    store_lds<R2, G::PAD>(y1[i], lds + G::LDS_WORDS, c, rb);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < R1::NI; i++) {
+    int c, rb, hi;
+    R1::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+    uint32_t z0[R1::E], z1[R1::E];
+    load_lds<R1, G::PAD>(z0, lds, c, rb);
+    load_lds<R1, G::PAD>(z1, lds + G::LDS_WORDS, c, rb);
+    item_bfly<R1::RB, false, LAZY, false>(z0, itw, s0 + R1::SL0, s0, hi, col0 + c, q, nf);
+    item_bfly<R1::RB, false, LAZY, false>(z1, itw, s0 + R1::SL0, s0, hi, col0 + c, q, nf);
+    store_global<R1>(z0, acc_e, 0, col0 + c, rb);
+    store_global<R1>(z1, acc_e + (size_t)A.E * N, 0, col0 + c, rb);
   }
 }
 
@@ -710,6 +745,7 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
   const int pe = e < A.level ? e : A.L + (e - A.level);
   const uint32_t q = T.mod[pe], minv = T.minv[pe];
   const uint2* tw = reinterpret_cast<const uint2*>(T.tw) + ((size_t)pe << A.log_n);
+  const uint2* itw = reinterpret_cast<const uint2*>(T.itw) + ((size_t)pe << A.log_n);
   const size_t N = (size_t)1 << A.log_n;
   const uint32_t* Xe = X + (size_t)job * (size_t)A.x_job + (size_t)e * N;
   const uint32_t* De = D + (size_t)job * (size_t)A.d_job + (size_t)e * N;
@@ -717,9 +753,9 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
   uint32_t* acc_e = acc + (size_t)job * (size_t)A.acc_job + (size_t)e * N;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
-    kip_b_body<LOGR, true>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, T.red[pe], tw);
+    kip_b_body<LOGR, true>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, T.red[pe], tw, itw);
   else
-    kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, T.red[pe], tw);
+    kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, T.red[pe], tw, itw);
 }
 
 // ------------------------------------------------------------------ job-table forms
@@ -853,16 +889,17 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int
   const int pe = e < level ? e : G.L + (e - level);
   const uint32_t q = T.mod[pe], minv = T.minv[pe];
   const uint2* tw = reinterpret_cast<const uint2*>(T.tw) + ((size_t)pe << log_n);
+  const uint2* itw = reinterpret_cast<const uint2*>(T.itw) + ((size_t)pe << log_n);
   const size_t N = (size_t)1 << log_n;
   const WsLayout lay(k, level, G.K, G.alpha, log_n);
   uint32_t* ws = jt[j].ws;
   const int col0 = tile * Geo<LOGR>::COLS;
   if (q < (1u << 30))
     kip_b_body<LOGR, true>(ws + lay.X + (size_t)e * N, ws + lay.D + (size_t)e * N, G.evk + (size_t)pe * N,
-                           ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, T.red[pe], tw);
+                           ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, T.red[pe], tw, itw);
   else
     kip_b_body<LOGR, false>(ws + lay.X + (size_t)e * N, ws + lay.D + (size_t)e * N, G.evk + (size_t)pe * N,
-                            ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, T.red[pe], tw);
+                            ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, T.red[pe], tw, itw);
 }
 
 template <bool FWD, bool PASSB>
@@ -903,6 +940,16 @@ int ntt_launch(const mick_params* prm, const uint32_t* src, uint32_t* dst, const
     launch_pass<false, true>(lb, grid, s, src, dst, map, prm->dt, log_n, la, site + 1);
     launch_pass<false, false>(la, grid, s, dst, dst, map, prm->dt, log_n, 0, site);
   }
+  return hip_error(hipGetLastError(), "ntt launch");
+}
+
+int intt_pass_a_launch(const mick_params* prm, uint32_t* buf, const LimbMap& map, int n_limbs, int n_jobs,
+                       hipStream_t s, int site) {
+  if (n_limbs <= 0 || n_jobs <= 0) return MICK_OK;
+  if (n_limbs > 65535 || n_jobs > 65535) return set_error(MICK_E_ARG, "too many limbs for one transform launch");
+  const int log_n = prm->log_n;
+  dim3 grid(1u << (log_n - kTileLog), (unsigned)n_limbs, (unsigned)n_jobs);
+  launch_pass<false, false>(prm->split_a, grid, s, buf, buf, map, prm->dt, log_n, 0, site);
   return hip_error(hipGetLastError(), "ntt launch");
 }
 
@@ -967,7 +1014,8 @@ int launch_ntt_jt(const mick_params* prm, const JobDesc* jt, int nj, int stage, 
     ProfScope ps(site + 1, s);
     launch_pass_jt<true, true>(lb, blocks, s, jt, nj, stage, G, prm->dt, la);
   } else {
-    {
+    // the accumulators' pass B ran inside the key-product kernel
+    if (stage != S_INTT_ACC) {
       ProfScope ps(site + 1, s);
       launch_pass_jt<false, true>(lb, blocks, s, jt, nj, stage, G, prm->dt, la);
     }

@@ -50,7 +50,9 @@ int launch_tensor(const mick_params* prm, const CtPtrs& in, long long in_job_str
 // new limbs (ntt.hip).  dsc: the d_t limbs in the coefficient domain, each
 // already multiplied by its qhat_j^-1.
 int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, ModupArgs A, int n_jobs, hipStream_t s);
-// Pass B of those transforms fused with the key inner product (ntt.hip).
+// Pass B of those transforms fused with the key inner product, followed by
+// the first pass (pass B) of the accumulators' inverse transform; acc holds
+// that pass's output (ntt.hip).
 int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,
                  KipArgs A, hipStream_t s);
 int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out, const MdArgs& A, int mu, int n_jobs,
