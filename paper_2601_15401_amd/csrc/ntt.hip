@@ -217,6 +217,52 @@ __device__ __forceinline__ void stage_tw_pass_a(uint2* ltwa, const uint2* tw) {
   for (int i = threadIdx.x; i < (1 << LOGR); i += kThreads) ltwa[i] = tw[i];
 }
 
+// The tile's pass-B twiddles staged in LDS: stage s0 + sl, block rr < 2^sl,
+// column c < COLS at COLS (2^sl - 1) + rr COLS + c.
+template <int COLS>
+struct TwLds {
+  const uint2* t;
+  int s0, c;
+  __device__ uint2 operator()(int s, int, int rr) const {
+    const int sl = s - s0;
+    return t[COLS * ((1 << sl) - 1) + rr * COLS + c];
+  }
+};
+
+// Stages the pass-B twiddles of the tile's first NSL stages (sl < NSL) in
+// the TwLds layout; every load is issued before the first LDS store.
+template <int COLS, int NSL, int NT>
+__device__ __forceinline__ void stage_tw_pass_b(uint2* ltw, const uint2* tw, int s0, int col0) {
+  constexpr int LOGC = __builtin_ctz(COLS);
+  constexpr int NTW = COLS * ((1 << NSL) - 1);
+  constexpr int IT = (NTW + NT - 1) / NT;
+  uint2 t[IT];
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int i = it * NT + threadIdx.x;
+    if (i < NTW) {
+      const int c = i & (COLS - 1);
+      const int k = i >> LOGC;  // (2^sl - 1) + rr
+      const int sl = 31 - __clz(k + 1);
+      const int rr = k + 1 - (1 << sl);
+      t[it] = tw[(1 << (s0 + sl)) + (rr << s0) + col0 + c];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int i = it * NT + threadIdx.x;
+    if (i < NTW) ltw[i] = t[it];
+  }
+}
+
+// LDS twiddle words of a transform pass: the forward pass A stages pass A's
+// twiddles; the inverse pass B at LOGR = 8 stages its strided round's
+// per-column twiddles (3.75 KB, which keeps four workgroups per CU).
+template <int LOGR, bool FWD, bool PASSB>
+constexpr int pass_tw_words() {
+  return FWD && !PASSB ? 1 << LOGR : (!FWD && PASSB && LOGR == 8 ? Geo<LOGR>::COLS * ((1 << Geo<LOGR>::RB0) - 1) : 1);
+}
+
 template <int RB, bool FWD, bool LAZY, bool HAS_STAGE0>
 __device__ __forceinline__ void item_bfly(uint32_t (&x)[1 << RB], const uint2* tw, int s_first, int s0, int hi,
                                           int blk, uint32_t q, const uint4& nfix) {
@@ -290,9 +336,9 @@ __device__ __forceinline__ void store_lds(const uint32_t (&x)[RD::E], uint32_t* 
 
 // ------------------------------------------------------------------ plain transform pass
 
-// ltwa: LDS for pass A's twiddles, used by the forward pass A, whose second
-// round reads per-thread twiddles after the barrier (the first round's are
-// uniform per wave).
+// ltwa: LDS twiddles (pass_tw_words) for the second round, which would
+// otherwise read per-thread twiddles right after the barrier: the forward
+// pass A (its first round's are uniform per wave) and the inverse pass B.
 template <int LOGR, bool FWD, bool LAZY, bool PASSB>
 __device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, uint32_t* lds, uint2* ltwa, int s0,
                                           int H, int col0, uint32_t q, const uint2* tw, const uint4& nfix) {
@@ -302,7 +348,9 @@ __device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, ui
   using R2 = Rnd<LOGR, PASSB, !FWD>;
   constexpr bool FINAL = FWD ? PASSB : !PASSB;  // last pass of the transform
   constexpr bool STAGED = FWD && !PASSB;
+  constexpr bool STAGED_B = !FWD && PASSB && LOGR == 8;
   if constexpr (STAGED) stage_tw_pass_a<LOGR>(ltwa, tw);
+  if constexpr (STAGED_B) stage_tw_pass_b<G::COLS, G::RB0, kThreads>(ltwa, tw, s0, col0);
 #pragma unroll
   for (int i = 0; i < R1::NI; i++) {
     int c, rb, hi;
@@ -322,6 +370,8 @@ __device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, ui
     // the inverse's strided round of pass A holds global stage 0
     if constexpr (STAGED)
       item_bfly_t<R2::RB, FWD, LAZY, false>(x, TwPassA{ltwa}, R2::SL0, hi, q, nfix);
+    else if constexpr (STAGED_B)
+      item_bfly_t<R2::RB, FWD, LAZY, false>(x, TwLds<G::COLS>{ltwa, s0, c}, s0 + R2::SL0, hi, q, nfix);
     else
       item_bfly<R2::RB, FWD, LAZY, !FWD && !PASSB>(x, tw, s0 + R2::SL0, s0, hi, PASSB ? col0 + c : 0, q, nfix);
     if constexpr (FINAL) {
@@ -344,7 +394,7 @@ template <int LOGR, bool FWD, bool PASSB>
 __global__ __launch_bounds__(kThreads) void k_ntt_pass(const uint32_t* src, uint32_t* dst, LimbMap mp, DevTables T,
                                                        int log_n, int s0) {
   __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
-  __shared__ uint2 ltwa[FWD && !PASSB ? 1 << LOGR : 1];
+  __shared__ uint2 ltwa[pass_tw_words<LOGR, FWD, PASSB>()];
   int prime, pos;
   size_t off;
   resolve(mp, blockIdx.y, log_n, prime, pos, off);
@@ -501,18 +551,6 @@ __global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint3
 
 constexpr int kKipThreads = 512;
 
-// The tile's pass-B twiddles staged in LDS: stage s0 + sl, block rr < 2^sl,
-// column c < COLS at COLS (2^sl - 1) + rr COLS + c.
-template <int COLS>
-struct TwLds {
-  const uint2* t;
-  int s0, c;
-  __device__ uint2 operator()(int s, int, int rr) const {
-    const int sl = s - s0;
-    return t[COLS * ((1 << sl) - 1) + rr * COLS + c];
-  }
-};
-
 template <int LOGR, bool LAZY>
 __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* De, const uint32_t* evk_e,
                                            uint32_t* acc_e, const KipArgs& A, uint32_t* lds, uint2* ltw, int e,
@@ -529,30 +567,8 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   // every (t, b) pair of this tile uses the same twiddles: stage them once.
   // A limb of the only digit (B = 1, e < level) is its own ModUp image in
   // every pair, so it transforms nothing and skips the staging.
-  // All loads are issued before the first LDS write, so the staging costs
-  // one memory latency, not one per iteration.
   const bool transforms = A.B > 1 || e >= A.level;
-  if (transforms) {
-    constexpr int NTW = G::COLS * ((1 << LOGR) - 1);
-    constexpr int IT = (NTW + kKipThreads - 1) / kKipThreads;
-    uint2 t[IT];
-#pragma unroll
-    for (int it = 0; it < IT; it++) {
-      const int i = it * kKipThreads + threadIdx.x;
-      if (i < NTW) {
-        const int c = i & (G::COLS - 1);
-        const int k = i >> G::LOGC;  // (2^sl - 1) + rr
-        const int sl = 31 - __clz(k + 1);
-        const int rr = k + 1 - (1 << sl);
-        t[it] = tw[(1 << (s0 + sl)) + (rr << s0) + col0 + c];
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; it++) {
-      const int i = it * kKipThreads + threadIdx.x;
-      if (i < NTW) ltw[i] = t[it];
-    }
-  }
+  if (transforms) stage_tw_pass_b<G::COLS, LOGR, kKipThreads>(ltw, tw, s0, col0);
   // pairs p = (t - 2) B + b.  A pair is "own" when limb e belongs to digit b:
   // its ModUp image is D_t itself (NTT domain, round-2 layout); otherwise the
   // pass-A output X_{t,b,e} is read in round-1 layout.
@@ -767,7 +783,7 @@ template <int LOGR, bool FWD, bool PASSB>
 __global__ __launch_bounds__(kThreads) void k_ntt_pass_jt(const JobDesc* jt, int nj, int stage, GroupConsts G,
                                                           DevTables T, int s0) {
   __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
-  __shared__ uint2 ltwa[FWD && !PASSB ? 1 << LOGR : 1];
+  __shared__ uint2 ltwa[pass_tw_words<LOGR, FWD, PASSB>()];
   constexpr bool FIRST = FWD ? !PASSB : PASSB;  // the transform's first pass reads the source
   const int j = find_job(jt, nj, stage, blockIdx.x);
   const int local = blockIdx.x - jt[j].blk0[stage];
