@@ -1006,7 +1006,7 @@ void job_blocks(const mick_params* prm, int k, int level, int (&nb)[kStages]) {
   nb[S_TENSOR] = pad8((prm->N / 1024) * level);
   nb[S_INTT_D] = pad8(tiles * (k - 1) * level);
   nb[S_MODUP] = pad8((k - 1) * B * tiles) * E;
-  nb[S_KIP] = pad8(E * tiles);
+  nb[S_KIP] = pad8(E * (1 << (prm->log_n - kKipTileLog)));
   nb[S_INTT_ACC] = pad8(tiles * 2 * E);
   nb[S_MODDOWN] = pad8(2 * (prm->N / 256));
   nb[S_NTT_OUT] = pad8(tiles * 2 * (level - k + 1));

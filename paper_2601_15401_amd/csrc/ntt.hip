@@ -53,9 +53,10 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTileLog = 13;
 
-template <int LOGR>
+// TL: log2 of the tile's element count (8192 for the transform passes).
+template <int LOGR, int TL = kTileLog>
 struct Geo {
-  static constexpr int LOGC = kTileLog - LOGR;
+  static constexpr int LOGC = TL - LOGR;
   static constexpr int COLS = 1 << LOGC;
   static constexpr int RB0 = (LOGR == 6) ? 3 : 4;
   static constexpr int RB1 = LOGR - RB0;
@@ -70,14 +71,14 @@ struct Geo {
 
 // Item layout of one round.  An item is one column c and 2^RB rows
 // rbase + j 2^NLO_LOG, j < 2^RB.
-template <int LOGR, bool PASSB, bool STRIDED, int NT = kThreads>
+template <int LOGR, bool PASSB, bool STRIDED, int NT = kThreads, int TL = kTileLog>
 struct Rnd {
-  using G = Geo<LOGR>;
+  using G = Geo<LOGR, TL>;
   static constexpr int RB = STRIDED ? G::RB0 : G::RB1;
   static constexpr int E = 1 << RB;
   static constexpr int SL0 = STRIDED ? 0 : G::RB0;  // first local stage of the round
   static constexpr int NLO_LOG = STRIDED ? LOGR - G::RB0 : 0;
-  static constexpr int ITEMS = (1 << kTileLog) >> RB;
+  static constexpr int ITEMS = (1 << TL) >> RB;
   static constexpr int NI = ITEMS / NT;  // items per thread
   // pass B's strided round walks the rows of a column with consecutive lanes
   static constexpr bool LO_FAST = PASSB && STRIDED;
@@ -549,16 +550,21 @@ __global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint3
 
 // ------------------------------------------------------------------ pass B + key inner product
 
-constexpr int kKipThreads = 512;
+// One wave per workgroup on 1024-element tiles: the pair loop's barriers
+// involve a single wave, and eight workgroups (20 KB of LDS each) share a
+// CU, which is what its 219-245 VGPRs allow.  (8192-element tiles with 512
+// threads: 1121 us per eight-job launch; 4096 / 256: 1075; 2048 / 128: 996;
+// 1024 / 64: 955.)
+constexpr int kKipThreads = 64;
 
 template <int LOGR, bool LAZY>
 __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* De, const uint32_t* evk_e,
                                            uint32_t* acc_e, const KipArgs& A, uint32_t* lds, uint2* ltw, int e,
                                            int col0, uint32_t q, uint32_t minv, const Red64& red, const uint2* tw,
                                            const uint2* itw) {
-  using G = Geo<LOGR>;
-  using R1 = Rnd<LOGR, true, true, kKipThreads>;
-  using R2 = Rnd<LOGR, true, false, kKipThreads>;
+  using G = Geo<LOGR, kKipTileLog>;
+  using R1 = Rnd<LOGR, true, true, kKipThreads, kKipTileLog>;
+  using R2 = Rnd<LOGR, true, false, kKipThreads, kKipTileLog>;
   constexpr int V = R1::NI * R1::E;  // words of the tile held by one thread
   static_assert(V == R2::NI * R2::E, "both rounds cover the tile");
   const size_t N = (size_t)1 << A.log_n;
@@ -750,8 +756,8 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
 template <int LOGR>
 __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const uint32_t* D, const uint32_t* evk,
                                                        uint32_t* acc, KipArgs A, DevTables T) {
-  __shared__ uint32_t lds[2 * Geo<LOGR>::LDS_WORDS];
-  __shared__ uint2 ltw[Geo<LOGR>::COLS * ((1 << LOGR) - 1)];
+  __shared__ uint32_t lds[2 * Geo<LOGR, kKipTileLog>::LDS_WORDS];
+  __shared__ uint2 ltw[Geo<LOGR, kKipTileLog>::COLS * ((1 << LOGR) - 1)];
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
   const int job = seq % A.n_jobs;
   const int unit = (seq / A.n_jobs) * 8 + xcd;  // (limb e, tile)
@@ -767,7 +773,7 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
   const uint32_t* De = D + (size_t)job * (size_t)A.d_job + (size_t)e * N;
   const uint32_t* evk_e = evk + (size_t)pe * N;
   uint32_t* acc_e = acc + (size_t)job * (size_t)A.acc_job + (size_t)e * N;
-  const int col0 = tile * Geo<LOGR>::COLS;
+  const int col0 = tile * Geo<LOGR, kKipTileLog>::COLS;
   if (q < (1u << 30))
     kip_b_body<LOGR, true>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, T.red[pe], tw, itw);
   else
@@ -880,8 +886,8 @@ __global__ __launch_bounds__(kThreads) void k_modup_a_jt(const JobDesc* jt, int 
 // ceil(E tiles / 8) 8.
 template <int LOGR>
 __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
-  __shared__ uint32_t lds[2 * Geo<LOGR>::LDS_WORDS];
-  __shared__ uint2 ltw[Geo<LOGR>::COLS * ((1 << LOGR) - 1)];
+  __shared__ uint32_t lds[2 * Geo<LOGR, kKipTileLog>::LDS_WORDS];
+  __shared__ uint2 ltw[Geo<LOGR, kKipTileLog>::COLS * ((1 << LOGR) - 1)];
   const int j = find_job(jt, nj, S_KIP, blockIdx.x);
   const int local = blockIdx.x - jt[j].blk0[S_KIP];
   const int log_n = G.log_n;
@@ -896,7 +902,7 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int
   A.dnum = G.dnum;
   A.k = k;
   A.n_jobs = 1;
-  A.tiles = 1 << (log_n - kTileLog);
+  A.tiles = 1 << (log_n - kKipTileLog);
   A.key_poly = (long long)(G.L + G.K) << log_n;
   const int unit = (local >> 3) * 8 + (local & 7);
   if (unit >= A.E * A.tiles) return;
@@ -909,7 +915,7 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int
   const size_t N = (size_t)1 << log_n;
   const WsLayout lay(k, level, G.K, G.alpha, log_n);
   uint32_t* ws = jt[j].ws;
-  const int col0 = tile * Geo<LOGR>::COLS;
+  const int col0 = tile * Geo<LOGR, kKipTileLog>::COLS;
   if (q < (1u << 30))
     kip_b_body<LOGR, true>(ws + lay.X + (size_t)e * N, ws + lay.D + (size_t)e * N, G.evk + (size_t)pe * N,
                            ws + lay.acc + (size_t)e * N, A, lds, ltw, e, col0, q, minv, T.red[pe], tw, itw);
@@ -1000,7 +1006,7 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
 
 int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,
                  KipArgs A, hipStream_t s) {
-  A.tiles = 1 << (prm->log_n - kTileLog);
+  A.tiles = 1 << (prm->log_n - kKipTileLog);
   const int units = A.E * A.tiles;
   const unsigned blocks = (unsigned)(((units + 7) / 8) * 8 * A.n_jobs);
   ProfScope ps(P_KIP, s);
