@@ -13,6 +13,7 @@ namespace mick {
 
 constexpr int kMaxK = 12;     // largest k of a k-input multiply
 constexpr int kKipTileLog = 10;  // log2 of the key-product kernel's tile (elements)
+constexpr int kModupTileLog = 13;  // log2 of the ModUp kernel's tile (elements)
 constexpr int kMaxJobs = 64;  // jobs per batched launch sequence
 
 // Device pointers to the per-prime tables.  Prime index j < L is q_j,

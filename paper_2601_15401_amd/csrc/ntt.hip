@@ -213,9 +213,9 @@ struct TwPassA {
   __device__ uint2 operator()(int s, int, int rr) const { return t[(1 << s) + rr]; }
 };
 
-template <int LOGR>
+template <int LOGR, int NT = kThreads>
 __device__ __forceinline__ void stage_tw_pass_a(uint2* ltwa, const uint2* tw) {
-  for (int i = threadIdx.x; i < (1 << LOGR); i += kThreads) ltwa[i] = tw[i];
+  for (int i = threadIdx.x; i < (1 << LOGR); i += NT) ltwa[i] = tw[i];
 }
 
 // The tile's pass-B twiddles staged in LDS: stage s0 + sl, block rr < 2^sl,
@@ -424,6 +424,13 @@ void launch_pass(int logr, dim3 grid, hipStream_t s, const uint32_t* src, uint32
 
 // ------------------------------------------------------------------ ModUp: conversion + pass A
 
+// 32 elements per thread on tiles of 2^kModupTileLog elements.  Unlike the
+// key-product kernel, ModUp loses with narrower tiles: its source rows are
+// read a tile row at a time, and a 4096- or 2048-element tile reads 64- or
+// 32-byte row segments (1262 us per eight-job launch at 8192 elements, 1503
+// at 4096, 2322 at 2048).
+constexpr int kModupThreads = 1 << (kModupTileLog - 5);
+
 // Workgroup order: the targets of one source tile run back to back on one
 // XCD (block b goes to XCD b % 8), so the source tile is read from L2.
 // The conversion constants carry a factor R = 2^32 (Montgomery form): the
@@ -434,19 +441,19 @@ template <int LOGR, int ALPHA, bool LAZY>
 __device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na, const uint32_t (&cc)[ALPHA],
                                              uint32_t minv, uint32_t* dst, uint32_t* lds, uint2* ltwa, int H,
                                              int col0, uint32_t q, const uint2* tw) {
-  using G = Geo<LOGR>;
-  using R1 = Rnd<LOGR, false, true>;
-  using R2 = Rnd<LOGR, false, false>;
+  using G = Geo<LOGR, kModupTileLog>;
+  using R1 = Rnd<LOGR, false, true, kModupThreads, kModupTileLog>;
+  using R2 = Rnd<LOGR, false, false, kModupThreads, kModupTileLog>;
   const uint4 nf{};
   // the second round's twiddles vary per thread: read from LDS after the barrier
-  stage_tw_pass_a<LOGR>(ltwa, tw);
+  stage_tw_pass_a<LOGR, kModupThreads>(ltwa, tw);
   // the item's rows are 2^NLO_LOG rows apart: a uniform byte step per j
   constexpr uint32_t kRowStep = 4u << R1::NLO_LOG;
   const uint32_t row_bytes = 4u << (H + LOGR);  // one source limb
 #pragma unroll
   for (int i = 0; i < R1::NI; i++) {
     int c, rb, hi;
-    R1::decode(i * kThreads + threadIdx.x, c, rb, hi);
+    R1::decode(i * kModupThreads + threadIdx.x, c, rb, hi);
     const uint32_t voff = 4u * R1::gidx(H, col0 + c, R1::row(rb, 0));
     uint32_t vj[R1::E];  // lane offsets of the item's positions in one limb
 #pragma unroll
@@ -498,7 +505,7 @@ __device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na,
 #pragma unroll
   for (int i = 0; i < R2::NI; i++) {
     int c, rb, hi;
-    R2::decode(i * kThreads + threadIdx.x, c, rb, hi);
+    R2::decode(i * kModupThreads + threadIdx.x, c, rb, hi);
     uint32_t x[R2::E];
     load_lds<R2, G::PAD>(x, lds, c, rb);
     item_bfly_t<R2::RB, true, LAZY, false>(x, TwPassA{ltwa}, R2::SL0, hi, q, nf);
@@ -513,8 +520,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, 
 }
 
 template <int LOGR, int ALPHA>
-__global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint32_t* X, ModupArgs A, DevTables T) {
-  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+__global__ __launch_bounds__(kModupThreads) void k_modup_a(const uint32_t* dsc, uint32_t* X, ModupArgs A,
+                                                           DevTables T) {
+  __shared__ uint32_t lds[Geo<LOGR, kModupTileLog>::LDS_WORDS];
   __shared__ uint2 ltwa[1 << LOGR];
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
   const int e = seq % A.E;
@@ -541,7 +549,7 @@ __global__ __launch_bounds__(kThreads) void k_modup_a(const uint32_t* dsc, uint3
   for (int a = 0; a < ALPHA; a++) cc[a] = C[a * A.E + e];
   uint32_t* dst = X + (size_t)job * (size_t)A.x_job + ((size_t)tb * A.E + e) * N;
   const int H = A.log_n - LOGR;
-  const int col0 = tile * Geo<LOGR>::COLS;
+  const int col0 = tile * Geo<LOGR, kModupTileLog>::COLS;
   if (q < (1u << 30))
     modup_a_body<LOGR, ALPHA, true>(src, na, cc, minv, dst, lds, ltwa, H, col0, q, tw);
   else
@@ -842,15 +850,15 @@ __global__ __launch_bounds__(kThreads) void k_ntt_pass_jt(const JobDesc* jt, int
 // ceil(units / 8) 8 E with units = (k - 1) B tiles (each job's first block is
 // a multiple of 8, so local and global blocks share their XCD).
 template <int LOGR, int ALPHA>
-__global__ __launch_bounds__(kThreads) void k_modup_a_jt(const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
-  __shared__ uint32_t lds[Geo<LOGR>::LDS_WORDS];
+__global__ __launch_bounds__(kModupThreads) void k_modup_a_jt(const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
+  __shared__ uint32_t lds[Geo<LOGR, kModupTileLog>::LDS_WORDS];
   __shared__ uint2 ltwa[1 << LOGR];
   const int j = find_job(jt, nj, S_MODUP, blockIdx.x);
   const int local = blockIdx.x - jt[j].blk0[S_MODUP];
   const int log_n = G.log_n;
   const int k = jt[j].k, level = jt[j].level;
   const int E = level + G.K, B = (level + G.alpha - 1) / G.alpha;
-  const int tiles = 1 << (log_n - kTileLog);
+  const int tiles = 1 << (log_n - kModupTileLog);
   const int units = (k - 1) * B * tiles;
   const int xcd = local & 7, seq = local >> 3;
   const int e = seq % E;
@@ -875,7 +883,7 @@ __global__ __launch_bounds__(kThreads) void k_modup_a_jt(const JobDesc* jt, int 
   for (int a = 0; a < ALPHA; a++) cc[a] = C[a * E + e];
   uint32_t* dst = jt[j].ws + lay.X + ((size_t)tb * E + e) * N;
   const int H = log_n - LOGR;
-  const int col0 = tile * Geo<LOGR>::COLS;
+  const int col0 = tile * Geo<LOGR, kModupTileLog>::COLS;
   if (q < (1u << 30))
     modup_a_body<LOGR, ALPHA, true>(src, na, cc, minv, dst, lds, ltwa, H, col0, q, tw);
   else
@@ -976,13 +984,13 @@ int intt_pass_a_launch(const mick_params* prm, uint32_t* buf, const LimbMap& map
 }
 
 int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, ModupArgs A, int n_jobs, hipStream_t s) {
-  A.tiles = 1 << (prm->log_n - kTileLog);
+  A.tiles = 1 << (prm->log_n - kModupTileLog);
   A.units = n_jobs * A.groups * A.tiles;
   const unsigned blocks = (unsigned)(((A.units + 7) / 8) * 8 * A.E);
   ProfScope ps(P_MODUP, s);
   const int la = prm->split_a;
   const DevTables& T = prm->dt;
-#define MICK_MA(LR, AL) k_modup_a<LR, AL><<<blocks, kThreads, 0, s>>>(dsc, X, A, T)
+#define MICK_MA(LR, AL) k_modup_a<LR, AL><<<blocks, kModupThreads, 0, s>>>(dsc, X, A, T)
 #define MICK_MA_A(LR)                      \
   switch (modup_rows(A.alpha)) {           \
     case 1: MICK_MA(LR, 1); break;         \
@@ -1052,7 +1060,7 @@ int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blo
   if (blocks <= 0) return MICK_OK;
   ProfScope ps(P_MODUP, s);
   const DevTables& T = prm->dt;
-#define MICK_MA(LR, AL) k_modup_a_jt<LR, AL><<<blocks, kThreads, 0, s>>>(jt, nj, G, T)
+#define MICK_MA(LR, AL) k_modup_a_jt<LR, AL><<<blocks, kModupThreads, 0, s>>>(jt, nj, G, T)
 #define MICK_MA_A(LR)                \
   switch (modup_rows(G.alpha)) {     \
     case 1: MICK_MA(LR, 1); break;   \
