@@ -353,6 +353,11 @@ int mick_ntt(const mick_params* prm, uint32_t* data_dev, int n_limbs, int first_
  * enabled, every kernel launch of the library is bracketed by a pair of HIP
  * events recorded on the launch's stream (process-wide switch). */
 int mick_profile_enable(int on);
+/* Restricts the recording to the named launch sites (comma-separated names
+ * as mick_profile_collect reports them, e.g. "modup_bconv_passA"); NULL or
+ * "" selects every site (the default).  MICK_E_ARG for an unknown name, the
+ * selection then unchanged.  Needs no device. */
+int mick_profile_select(const char* sites);
 /* Waits for the recorded events, then returns the number of launch sites
  * seen (at most `max`) with, per site, a static name, the summed kernel time
  * in milliseconds and the number of launches; clears the records. */

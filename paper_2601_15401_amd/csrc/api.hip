@@ -38,12 +38,13 @@ const char* const kSiteNames[P_COUNT] = {
     "rescale_sums", "rescale_combine", "ntt_other.passA", "ntt_other.passB"};
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+uint32_t g_prof_mask = ~0u;  // sites that record while profiling is on
 std::vector<hipEvent_t> g_prof_events;            // pool, two per record
 std::vector<std::pair<int, int>> g_prof_records;  // (site, first event index)
 }  // namespace
 
 ProfScope::ProfScope(int site_, hipStream_t s) : site(site_), idx(-1), stream(s) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || !((g_prof_mask >> site) & 1u)) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   size_t need = 2 * (g_prof_records.size() + 1);
   while (g_prof_events.size() < need) {
@@ -964,6 +965,30 @@ int mick_mul_relin_rescale_batch(const mick_params* prm, const mick_keys* keys, 
 int mick_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = on != 0;
+  return MICK_OK;
+}
+
+int mick_profile_select(const char* sites) {
+  static_assert(P_COUNT <= 32, "one mask bit per site");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!sites || !*sites) {
+    g_prof_mask = ~0u;
+    return MICK_OK;
+  }
+  uint32_t mask = 0;
+  std::string all(sites);
+  size_t pos = 0;
+  while (pos <= all.size()) {
+    const size_t end = std::min(all.find(',', pos), all.size());
+    const std::string name = all.substr(pos, end - pos);
+    int found = -1;
+    for (int i = 0; i < P_COUNT; i++)
+      if (name == kSiteNames[i]) found = i;
+    if (found < 0) return set_error(MICK_E_ARG, "unknown profiling site: " + name);
+    mask |= 1u << found;
+    pos = end + 1;
+  }
+  g_prof_mask = mask;
   return MICK_OK;
 }
 

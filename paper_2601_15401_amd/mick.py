@@ -78,6 +78,7 @@ _SIGS = {
     "mick_params_schedule": (ctypes.c_int, [_vp]),
     "mick_set_allocator": (ctypes.c_int, [_vp, _vp, _vp]),
     "mick_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "mick_profile_select": (ctypes.c_int, [ctypes.c_char_p]),
     "mick_profile_collect": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
 }
@@ -399,6 +400,12 @@ def ntt(prm: Params, data: torch.Tensor, first_prime: int, inverse: bool = False
 def profile_enable(on: bool = True):
     """Bracket every library kernel launch with HIP events on its stream."""
     _check(load().mick_profile_enable(int(on)), "mick_profile_enable")
+
+
+def profile_select(sites=None):
+    """Record only the named sites while profiling is on (None: every site)."""
+    arg = None if not sites else ",".join(sites).encode()
+    _check(load().mick_profile_select(arg), "mick_profile_select")
 
 
 def profile_collect():

@@ -109,3 +109,14 @@ def test_tree_planner_and_shapes_without_gpu():
     buf = (ctypes.c_int * 2)()
     assert lib.mick_tree_plan(12, buf, 2) == -1                         # too few token slots
     assert lib.mick_tree_plan(1, buf, 2) == -1
+
+
+def test_profile_site_selection_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    lib.mick_profile_select.argtypes = [ctypes.c_char_p]
+    assert lib.mick_profile_select(b"modup_bconv_passA") == 0
+    assert lib.mick_profile_select(b"passB_kip,intt_d.passA") == 0
+    assert lib.mick_profile_select(b"no_such_site") == -1
+    assert lib.mick_profile_select(b"tensor,") == -1  # an empty name is not a site
+    assert lib.mick_profile_select(None) == 0
+    assert lib.mick_profile_select(b"") == 0
