@@ -10,9 +10,10 @@
 //
 // Two passes cover the log N stages: pass A the first LA stages (element
 // pairs that differ in the high LA index bits), pass B the last LB stages.
-// A workgroup owns an 8192-element tile of one limb: 2^LOGR butterfly rows
-// by 8192 / 2^LOGR independent columns (pass A: columns are consecutive low
-// indices; pass B: columns are consecutive 2^LB-element blocks).  A pass is
+// A workgroup owns a tile of one limb (8192 elements; 1024 in the key-product
+// kernel): 2^LOGR butterfly rows by tile / 2^LOGR independent columns (pass
+// A: columns are consecutive low indices; pass B: columns are consecutive
+// 2^LB-element blocks).  A pass is
 // two radix-8/16 rounds in registers: the "strided" round (the pass's first
 // RB0 stages, row stride 2^(LOGR-RB0)) and the "consecutive" round (the last
 // RB1 stages, 2^RB1 neighbouring rows).  The first round of a pass loads
