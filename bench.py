@@ -129,16 +129,26 @@ def roofline(prof, steps, N, k, level, K, alpha, jobs):
             "algorithmic_bytes_per_launch": b, "alu_frac": round(alu_frac, 4)}
 
 
+def _code_tokens(text):
+    """C/C++ source without comments and with whitespace collapsed (string
+    and character literals are kept as they are)."""
+    import re
+    pat = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'', re.S)
+    code = pat.sub(lambda m: " " if m.group(0).startswith("/") else m.group(0), text)
+    return " ".join(code.split())
+
+
 def kernel_source_hash():
     """First 16 hex digits of a SHA-256 over the kernel sources (csrc/*.hip,
-    csrc/*.h in name order), recorded with the counter summaries."""
+    csrc/*.h in name order, comments and whitespace ignored), recorded with
+    the counter summaries."""
     import glob
     import hashlib
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2601_15401_amd", "csrc", "*.hip")) +
                     glob.glob(os.path.join(ROOT, "paper_2601_15401_amd", "csrc", "*.h"))):
         h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+        h.update(_code_tokens(open(f, encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -60,3 +60,13 @@ def test_transform_pass_work_is_half_the_transform(monkeypatch):
     assert ops == n * (N / 2) * 16 * 9.0  # 16 stages of N/2 butterflies
     rl = bench.roofline({"intt_d.passA": (5.0, 20)}, 20, N, k, level, K, alpha, jobs)
     assert abs(rl["alu_frac"] - (ops / 2) / 250e-6 / 1e12 / bench.ALU_PEAK_TOPS) < 1e-3
+
+
+def test_source_hash_ignores_comments_and_whitespace():
+    a = 'int f(int x) {  // doubles\n  return 2 * x; /* no overflow\n here */ }\nconst char* s = "a // b";\n'
+    b = 'int f(int x) { return 2 * x; }\nconst char* s = "a // b";'
+    c = 'int f(int x) { return 3 * x; }\nconst char* s = "a // b";'
+    d = 'int f(int x) { return 2 * x; }\nconst char* s = "a  b";'
+    assert bench._code_tokens(a) == bench._code_tokens(b)
+    assert bench._code_tokens(b) != bench._code_tokens(c)
+    assert bench._code_tokens(b) != bench._code_tokens(d)  # literals are code
