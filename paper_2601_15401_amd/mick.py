@@ -130,9 +130,16 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t: torch.Tensor):
+def _ptr(t: torch.Tensor, n: int = 0, what: str = "buffer"):
+    """Device address of a contiguous int32 CUDA tensor.  n > 0: the number of
+    words the library reads or writes there (the C ABI takes bare pointers, so
+    a buffer of another size is refused here rather than overrun on the GPU).
+    n <= 0 leaves the size to the library's own argument checks, which reject
+    such shapes before touching memory."""
     if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.int32:
-        raise ValueError("expected a contiguous int32 CUDA tensor")
+        raise ValueError("%s: expected a contiguous int32 CUDA tensor" % what)
+    if n > 0 and t.numel() != n:
+        raise ValueError("%s: expected %d int32 words, got %d" % (what, n, t.numel()))
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -231,21 +238,21 @@ def encrypt(prm: Params, keys: Keys, m: np.ndarray, level: int, seed: int, ct_id
     m = np.ascontiguousarray(m, dtype=np.int64)
     if out is None:
         out = _dev_empty(2, level, prm.N)
-    _check(load().mick_encrypt(prm.handle, keys.handle, m.ctypes.data_as(_c_i64p), level, seed, ct_id, _ptr(out),
+    _check(load().mick_encrypt(prm.handle, keys.handle, m.ctypes.data_as(_c_i64p), level, seed, ct_id, _ptr(out, 2 * level * prm.N, "out"),
                                _stream()), "mick_encrypt")
     return out
 
 
 def decrypt_residues(prm: Params, keys: Keys, ct: torch.Tensor, level: int) -> np.ndarray:
     out = np.empty((level, prm.N), dtype=np.uint32)
-    _check(load().mick_decrypt_residues(prm.handle, keys.handle, _ptr(ct), level, out.ctypes.data_as(_c_u32p),
+    _check(load().mick_decrypt_residues(prm.handle, keys.handle, _ptr(ct, 2 * level * prm.N, "ct"), level, out.ctypes.data_as(_c_u32p),
                                         _stream()), "mick_decrypt_residues")
     return out
 
 
 def decrypt(prm: Params, keys: Keys, ct: torch.Tensor, level: int) -> np.ndarray:
     out = np.empty(prm.N, dtype=np.int64)
-    _check(load().mick_decrypt(prm.handle, keys.handle, _ptr(ct), level, out.ctypes.data_as(_c_i64p), _stream()),
+    _check(load().mick_decrypt(prm.handle, keys.handle, _ptr(ct, 2 * level * prm.N, "ct"), level, out.ctypes.data_as(_c_i64p), _stream()),
            "mick_decrypt")
     return out
 
@@ -261,8 +268,9 @@ def mul_k(prm: Params, cts: Sequence[torch.Tensor], level: int, out=None) -> tor
     k = len(cts)
     if out is None:
         out = _dev_empty(k + 1, level, prm.N)
-    arr = (_vp * k)(*[_ptr(c).value for c in cts])
-    _check(load().mick_mul_k(prm.handle, arr, k, level, _ptr(out), _stream()), "mick_mul_k")
+    arr = (_vp * k)(*[_ptr(c, 2 * level * prm.N, "ct").value for c in cts])
+    _check(load().mick_mul_k(prm.handle, arr, k, level, _ptr(out, (k + 1) * level * prm.N, "out"), _stream()),
+           "mick_mul_k")
     return out
 
 
@@ -271,7 +279,8 @@ def relin_k(prm: Params, keys: Keys, d: torch.Tensor, k: int, level: int, out=No
         out = _dev_empty(2, level, prm.N)
     if ws is None:
         ws = workspace(prm, OP_RELIN, k, level)
-    _check(load().mick_relin_k(prm.handle, keys.handle, _ptr(d), k, level, _ptr(out), _ptr(ws), ws.numel() * 4,
+    _check(load().mick_relin_k(prm.handle, keys.handle, _ptr(d, (k + 1) * level * prm.N, "d"), k, level,
+                               _ptr(out, 2 * level * prm.N, "out"), _ptr(ws), ws.numel() * 4,
                                _stream()), "mick_relin_k")
     return out
 
@@ -281,7 +290,8 @@ def rescale_multi(prm: Params, ct: torch.Tensor, level: int, mu: int, out=None, 
         out = _dev_empty(2, level - mu, prm.N)
     if ws is None:
         ws = workspace(prm, OP_RESCALE, mu, level)
-    _check(load().mick_rescale_multi(prm.handle, _ptr(ct), level, mu, _ptr(out), _ptr(ws), ws.numel() * 4,
+    _check(load().mick_rescale_multi(prm.handle, _ptr(ct, 2 * level * prm.N, "ct"), level, mu,
+                                     _ptr(out, 2 * (level - mu) * prm.N, "out"), _ptr(ws), ws.numel() * 4,
                                      _stream()), "mick_rescale_multi")
     return out
 
@@ -293,8 +303,9 @@ def mul_relin_rescale(prm: Params, keys: Keys, cts: Sequence[torch.Tensor], leve
         out = _dev_empty(2, level - k + 1, prm.N)
     if ws is None:
         ws = workspace(prm, OP_MUL_RELIN_RESCALE, k, level)
-    arr = (_vp * k)(*[_ptr(c).value for c in cts])
-    _check(load().mick_mul_relin_rescale(prm.handle, keys.handle, arr, k, level, _ptr(out), _ptr(ws),
+    arr = (_vp * k)(*[_ptr(c, 2 * level * prm.N, "ct").value for c in cts])
+    _check(load().mick_mul_relin_rescale(prm.handle, keys.handle, arr, k, level,
+                                         _ptr(out, 2 * (level - k + 1) * prm.N, "out"), _ptr(ws),
                                          ws.numel() * 4, _stream()), "mick_mul_relin_rescale")
     return out
 
@@ -316,7 +327,8 @@ def mul_relin_rescale_batch(prm: Params, keys: Keys, cts: torch.Tensor, level: i
         out = _dev_empty(n_jobs, 2, level - k + 1, prm.N)
     if ws is None:
         ws = batch_workspace(prm, n_jobs, k, level)
-    _check(load().mick_mul_relin_rescale_batch(prm.handle, keys.handle, _ptr(cts), n_jobs, k, level, _ptr(out),
+    _check(load().mick_mul_relin_rescale_batch(prm.handle, keys.handle, _ptr(cts), n_jobs, k, level,
+                                               _ptr(out, n_jobs * 2 * (level - k + 1) * prm.N, "out"),
                                                _ptr(ws), ws.numel() * 4, _stream()), "mick_mul_relin_rescale_batch")
     return out
 
@@ -333,8 +345,8 @@ def make_jobs(prm: Params, specs):
             out = _dev_empty(2, level - k + 1, prm.N)
         arr[i].k, arr[i].level = k, level
         for u, c in enumerate(cts):
-            arr[i].cts[u] = _ptr(c).value
-        arr[i].out = _ptr(out).value
+            arr[i].cts[u] = _ptr(c, 2 * level * prm.N, "ct").value
+        arr[i].out = _ptr(out, 2 * (level - k + 1) * prm.N, "out").value
         outs.append(out)
     return arr, outs
 
@@ -393,6 +405,8 @@ class Plan:
 
 def ntt(prm: Params, data: torch.Tensor, first_prime: int, inverse: bool = False) -> torch.Tensor:
     """In-place transform of data [n_limbs, N]; limb i uses prime index first_prime + i."""
+    if data.dim() != 2 or data.shape[1] != prm.N:
+        raise ValueError("data must be [n_limbs, N]")
     _check(load().mick_ntt(prm.handle, _ptr(data), data.shape[0], first_prime, int(inverse), _stream()), "mick_ntt")
     return data
 
@@ -447,9 +461,11 @@ class Queue:
         arr = (QJob * len(jobs))()
         for i, (jid, st, cts, level, out) in enumerate(jobs):
             arr[i].id, arr[i].set, arr[i].k, arr[i].level = jid, st, len(cts), level
+            # an unknown set index is the library's to reject
+            N = self.sets[st][0].N if 0 <= st < len(self.sets) else 0
             for u, c in enumerate(cts):
-                arr[i].cts[u] = _ptr(c).value
-            arr[i].out = _ptr(out).value
+                arr[i].cts[u] = _ptr(c, 2 * level * N, "ct").value
+            arr[i].out = _ptr(out, 2 * (level - len(cts) + 1) * N, "out").value
         _check(load().mick_queue_push(self._h, ctypes.cast(arr, _vp), len(jobs)), "mick_queue_push")
         for jid, _st, cts, _lv, out in jobs:
             self._live[jid] = (cts, out)
@@ -635,7 +651,8 @@ def mul_tree(prm: Params, keys: Keys, cts: Sequence[torch.Tensor], level: int, t
         out = _dev_empty(2, level - depth, prm.N)
     if ws is None:
         ws = tree_workspace(prm, tree, level)
-    ptrs = (_vp * n)(*[_ptr(c).value for c in cts])
-    _check(load().mick_mul_tree(prm.handle, keys.handle, ptrs, level, arr, k, _ptr(out), _ptr(ws), ws.numel() * 4,
+    ptrs = (_vp * n)(*[_ptr(c, 2 * level * prm.N, "ct").value for c in cts])
+    _check(load().mick_mul_tree(prm.handle, keys.handle, ptrs, level, arr, k,
+                                _ptr(out, 2 * (level - depth) * prm.N, "out"), _ptr(ws), ws.numel() * 4,
                                 _stream()), "mick_mul_tree")
     return out

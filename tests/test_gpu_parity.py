@@ -245,6 +245,28 @@ def test_repeated_calls_are_deterministic(hyb):
         assert torch.equal(mick.mul_relin_rescale(c.prm, c.gk, cts, 6, ws=ws), ref)
 
 
+def test_binding_refuses_buffers_of_the_wrong_size(hyb):
+    """The C ABI takes bare device pointers; the binding checks each buffer's
+    size against the shape the call implies before any launch."""
+    c = hyb
+    N = c.prm.N
+    z = lambda *shape: torch.zeros(*shape, dtype=torch.int32, device="cuda")
+    ct8 = z(2, 8, N)
+    with pytest.raises(ValueError, match="ct"):
+        mick.mul_relin_rescale(c.prm, c.gk, [ct8, ct8, z(2, 7, N)], 8)
+    with pytest.raises(ValueError, match="out"):
+        mick.mul_relin_rescale(c.prm, c.gk, [ct8] * 3, 8, out=z(2, 5, N))
+    with pytest.raises(ValueError, match="out"):
+        mick.mul_k(c.prm, [ct8] * 3, 8, out=z(3, 8, N))
+    with pytest.raises(ValueError, match="d"):
+        mick.relin_k(c.prm, c.gk, z(3, 8, N), 3, 8)
+    with pytest.raises(ValueError, match="ct"):
+        mick.rescale_multi(c.prm, z(2, 7, N), 8, 2)
+    with pytest.raises(ValueError):
+        mick.ntt(c.prm, z(N), 0)
+    torch.cuda.synchronize()
+
+
 def test_error_codes(hyb):
     c = hyb
     ct = torch.zeros(2, 4, c.prm.N, dtype=torch.int32, device="cuda")
