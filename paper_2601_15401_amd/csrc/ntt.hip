@@ -434,6 +434,8 @@ constexpr int kModupThreads = 1 << (kModupTileLog - 5);
 
 // Workgroup order: the targets of one source tile run back to back on one
 // XCD (block b goes to XCD b % 8), so the source tile is read from L2.
+// One target per workgroup, except for same-shape launches at digits of 5
+// to 8 primes, which take two (k_modup_a2).
 // The conversion constants carry a factor R = 2^32 (Montgomery form): the
 // sum of up to 8 products of a residue below 2^30 and a constant below m
 // stays below 2m 2^32, so one Montgomery reduction returns it mod m (wider
@@ -555,6 +557,180 @@ __global__ __launch_bounds__(kModupThreads) void k_modup_a(const uint32_t* dsc, 
     modup_a_body<LOGR, ALPHA, true>(src, na, cc, minv, dst, lds, ltwa, H, col0, q, tw);
   else
     modup_a_body<LOGR, ALPHA, false>(src, na, cc, minv, dst, lds, ltwa, H, col0, q, tw);
+}
+
+// Two targets per workgroup: each source word loaded feeds both targets'
+// conversions, which halves the source traffic through L1.  The first
+// target's pass runs through the LDS tile while the second target's
+// converted values wait in registers; then the second target's pass.
+template <int LOGR, int ALPHA, bool LAZY>
+__device__ __forceinline__ void modup_a2_body(__amdgpu_buffer_rsrc_t src, int na, const uint32_t (&c0)[ALPHA],
+                                              const uint32_t (&c1)[ALPHA], uint32_t minv0, uint32_t minv1,
+                                              uint32_t* dst0, uint32_t* dst1, uint32_t* lds, uint2* ltw0, uint2* ltw1,
+                                              int H, int col0, uint32_t q0, uint32_t q1, const uint2* tw0,
+                                              const uint2* tw1) {
+  using G = Geo<LOGR, kModupTileLog>;
+  using R1 = Rnd<LOGR, false, true, kModupThreads, kModupTileLog>;
+  using R2 = Rnd<LOGR, false, false, kModupThreads, kModupTileLog>;
+  static_assert(ALPHA == 8, "eight rows: one reduction per sum");
+  const uint4 nf{};
+  stage_tw_pass_a<LOGR, kModupThreads>(ltw0, tw0);
+  stage_tw_pass_a<LOGR, kModupThreads>(ltw1, tw1);
+  constexpr uint32_t kRowStep = 4u << R1::NLO_LOG;
+  const uint32_t row_bytes = 4u << (H + LOGR);
+  uint32_t y1[R1::NI][R1::E];
+#pragma unroll
+  for (int i = 0; i < R1::NI; i++) {
+    int c, rb, hi;
+    R1::decode(i * kModupThreads + threadIdx.x, c, rb, hi);
+    const uint32_t voff = 4u * R1::gidx(H, col0 + c, R1::row(rb, 0));
+    uint32_t vj[R1::E];
+#pragma unroll
+    for (int j = 0; j < R1::E; j++) vj[j] = voff + ((uint32_t)j * kRowStep << H);
+    uint64_t a0[R1::E], a1[R1::E];
+#pragma unroll
+    for (int j = 0; j < R1::E; j++) a0[j] = a1[j] = 0;
+    uint32_t v[2][R1::E];
+#pragma unroll
+    for (int j = 0; j < R1::E; j++) v[0][j] = __builtin_amdgcn_raw_buffer_load_b32(src, vj[j], 0, 0);
+#pragma unroll
+    for (int a = 0; a < ALPHA; a++) {
+      if (a + 1 < ALPHA) {
+        const uint32_t soff = (uint32_t)min(a + 1, na - 1) * row_bytes;
+#pragma unroll
+        for (int j = 0; j < R1::E; j++)
+          v[(a + 1) & 1][j] = __builtin_amdgcn_raw_buffer_load_b32(src, vj[j], soff, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < R1::E; j++) {
+        a0[j] += (uint64_t)v[a & 1][j] * c0[a];
+        a1[j] += (uint64_t)v[a & 1][j] * c1[a];
+        // both sums advance with the row (the optimiser would otherwise
+        // finish one chain first and keep every source word for the other)
+        asm volatile("" : "+v"(a0[j]), "+v"(a1[j]));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    uint32_t x[R1::E];
+#pragma unroll
+    for (int j = 0; j < R1::E; j++) {
+      x[j] = redc_2m(a0[j], q0, minv0);
+      y1[i][j] = redc_2m(a1[j], q1, minv1);
+      asm volatile("" : "+v"(x[j]), "+v"(y1[i][j]));  // both sums reduced before the butterflies
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    item_bfly<R1::RB, true, LAZY, false>(x, tw0, R1::SL0, 0, hi, 0, q0, nf);
+    store_lds<R1, G::PAD>(x, lds, c, rb);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < R2::NI; i++) {
+    int c, rb, hi;
+    R2::decode(i * kModupThreads + threadIdx.x, c, rb, hi);
+    uint32_t x[R2::E];
+    load_lds<R2, G::PAD>(x, lds, c, rb);
+    item_bfly_t<R2::RB, true, LAZY, false>(x, TwPassA{ltw0}, R2::SL0, hi, q0, nf);
+    store_global<R2>(x, dst0, H, col0 + c, rb);
+  }
+  if (!dst1) return;  // uniform: an odd target count leaves one alone
+  // The second target's LDS addresses are those of the first: an opaque
+  // copy of the thread index makes the compiler recompute them here rather
+  // than hold them (in scratch) across both passes.
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < R1::NI; i++) {
+    int c, rb, hi;
+    R1::decode(i * kModupThreads + tid, c, rb, hi);
+    // the second target's round 1 runs here: its twiddles are not live
+    // through the first target's pass
+    item_bfly<R1::RB, true, LAZY, false>(y1[i], tw1, R1::SL0, 0, hi, 0, q1, nf);
+    store_lds<R1, G::PAD>(y1[i], lds, c, rb);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < R2::NI; i++) {
+    int c, rb, hi;
+    R2::decode(i * kModupThreads + tid, c, rb, hi);
+    uint32_t x[R2::E];
+    load_lds<R2, G::PAD>(x, lds, c, rb);
+    item_bfly_t<R2::RB, true, LAZY, false>(x, TwPassA{ltw1}, R2::SL0, hi, q1, nf);
+    store_global<R2>(x, dst1, H, col0 + c, rb);
+  }
+}
+
+// Digits of 5 to 8 primes, same-shape launches.  Target pairs of one source
+// tile: the digit's q targets (every q limb outside the digit) two by two,
+// then the special primes two by two, so both members of a pair take the
+// same lazy or canonical butterflies.  modup_pairs() pairs per unit is an
+// upper bound; the unused ones return, and an odd group's last target is
+// alone (e1 < 0).
+// Three waves per SIMD: 148 VGPRs (both targets' 64-bit sums, the next
+// source row, the second target's converted values) and no scratch.  Per
+// eight-job launch at the eight-input shape: 1277 us for the one-target
+// kernel at four waves, 1085 us here; forced to four waves this kernel
+// spills and takes 1169 us.  The job-table launch keeps the one-target
+// kernel: a job-table copy of this one in the same module changed the
+// compiler's register allocation of this one and gave back half its gain.
+template <int LOGR, int ALPHA>
+__global__ __launch_bounds__(kModupThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_modup_a2(
+    const uint32_t* dsc, uint32_t* X, ModupArgs A, DevTables T) {
+  __shared__ uint32_t lds[Geo<LOGR, kModupTileLog>::LDS_WORDS];
+  __shared__ uint2 ltw[2][1 << LOGR];
+  const int pairs = modup_pairs(A.level, A.E);
+  const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
+  const int pr = seq % pairs;
+  const int unit = (seq / pairs) * 8 + xcd;  // (job, t, b, tile)
+  if (unit >= A.units) return;
+  const int tile = unit % A.tiles;
+  const int src_grp = unit / A.tiles;
+  const int job = src_grp / A.groups;
+  const int tb = src_grp - job * A.groups;  // (t - 2) * B + b
+  const int t2 = tb / A.B, b = tb - t2 * A.B;
+  const int lo = b * A.alpha;
+  const int na = min(A.alpha, A.level - lo);
+  const int nq = A.level - na;
+  const int qp = (nq + 1) / 2;
+  int e0, e1;
+  if (pr < qp) {
+    const int i0 = 2 * pr, i1 = i0 + 1;
+    e0 = i0 < lo ? i0 : i0 + na;
+    e1 = i1 < nq ? (i1 < lo ? i1 : i1 + na) : -1;
+  } else {
+    e0 = A.level + 2 * (pr - qp);
+    if (e0 >= A.E) return;
+    e1 = e0 + 1 < A.E ? e0 + 1 : -1;
+  }
+  const bool two = e1 >= 0;
+  const int f1 = two ? e1 : e0;
+  const int p0 = e0 < A.level ? e0 : A.L + (e0 - A.level);
+  const int p1 = f1 < A.level ? f1 : A.L + (f1 - A.level);
+  const uint32_t q0 = T.mod[p0], q1 = T.mod[p1];
+  const uint2* tw0 = reinterpret_cast<const uint2*>(T.tw) + ((size_t)p0 << A.log_n);
+  const uint2* tw1 = reinterpret_cast<const uint2*>(T.tw) + ((size_t)p1 << A.log_n);
+  const size_t N = (size_t)1 << A.log_n;
+  const uint32_t* C = A.tab + A.tab_off[b] + 2 * ALPHA;
+  const uint32_t* base = dsc + (size_t)job * (size_t)A.dcoef_job + ((size_t)t2 * A.level + lo) * N;
+  const __amdgpu_buffer_rsrc_t src = buffer_rsrc(base, (uint32_t)(na * N * 4));
+  uint32_t c0[ALPHA], c1[ALPHA];
+#pragma unroll
+  for (int a = 0; a < ALPHA; a++) {
+    c0[a] = C[a * A.E + e0];
+    c1[a] = C[a * A.E + f1];
+  }
+  uint32_t* xj = X + (size_t)job * (size_t)A.x_job + (size_t)tb * A.E * N;
+  uint32_t* dst0 = xj + (size_t)e0 * N;
+  uint32_t* dst1 = two ? xj + (size_t)e1 * N : nullptr;
+  const int H = A.log_n - LOGR;
+  const int col0 = tile * Geo<LOGR, kModupTileLog>::COLS;
+  if (q0 < (1u << 30) && q1 < (1u << 30))
+    modup_a2_body<LOGR, ALPHA, true>(src, na, c0, c1, T.minv[p0], T.minv[p1], dst0, dst1, lds, ltw[0], ltw[1], H,
+                                     col0, q0, q1, tw0, tw1);
+  else
+    modup_a2_body<LOGR, ALPHA, false>(src, na, c0, c1, T.minv[p0], T.minv[p1], dst0, dst1, lds, ltw[0], ltw[1], H,
+                                      col0, q0, q1, tw0, tw1);
 }
 
 // ------------------------------------------------------------------ pass B + key inner product
@@ -987,29 +1163,31 @@ int intt_pass_a_launch(const mick_params* prm, uint32_t* buf, const LimbMap& map
 int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, ModupArgs A, int n_jobs, hipStream_t s) {
   A.tiles = 1 << (prm->log_n - kModupTileLog);
   A.units = n_jobs * A.groups * A.tiles;
-  const unsigned blocks = (unsigned)(((A.units + 7) / 8) * 8 * A.E);
+  const unsigned blocks =
+      (unsigned)(((A.units + 7) / 8) * 8 * (modup_two_targets(A.alpha) ? modup_pairs(A.level, A.E) : A.E));
   ProfScope ps(P_MODUP, s);
-  const int la = prm->split_a;
   const DevTables& T = prm->dt;
+#define MICK_MA2(LR, AL) k_modup_a2<LR, AL><<<blocks, kModupThreads, 0, s>>>(dsc, X, A, T)
 #define MICK_MA(LR, AL) k_modup_a<LR, AL><<<blocks, kModupThreads, 0, s>>>(dsc, X, A, T)
-#define MICK_MA_A(LR)                      \
-  switch (modup_rows(A.alpha)) {           \
-    case 1: MICK_MA(LR, 1); break;         \
-    case 2: MICK_MA(LR, 2); break;         \
-    case 4: MICK_MA(LR, 4); break;         \
-    case 8: MICK_MA(LR, 8); break;         \
-    case 16: MICK_MA(LR, 16); break;       \
-    case 24: MICK_MA(LR, 24); break;       \
-    case 32: MICK_MA(LR, 32); break;       \
+#define MICK_MA_A(LR)                                                   \
+  switch (modup_rows(A.alpha)) {                                        \
+    case 1: MICK_MA(LR, 1); break;                                      \
+    case 2: MICK_MA(LR, 2); break;                                      \
+    case 4: MICK_MA(LR, 4); break;                                      \
+    case 8: MICK_MA2(LR, 8); break;                                     \
+    case 16: MICK_MA(LR, 16); break;                                    \
+    case 24: MICK_MA(LR, 24); break;                                    \
+    case 32: MICK_MA(LR, 32); break;                                    \
     default: return set_error(MICK_E_ARG, "digit width out of range"); \
   }
-  if (la == 7) {
+  if (prm->split_a == 7) {
     MICK_MA_A(7)
   } else {
     MICK_MA_A(8)
   }
 #undef MICK_MA_A
 #undef MICK_MA
+#undef MICK_MA2
   return hip_error(hipGetLastError(), "modup launch");
 }
 
@@ -1062,15 +1240,15 @@ int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blo
   ProfScope ps(P_MODUP, s);
   const DevTables& T = prm->dt;
 #define MICK_MA(LR, AL) k_modup_a_jt<LR, AL><<<blocks, kModupThreads, 0, s>>>(jt, nj, G, T)
-#define MICK_MA_A(LR)                \
-  switch (modup_rows(G.alpha)) {     \
-    case 1: MICK_MA(LR, 1); break;   \
-    case 2: MICK_MA(LR, 2); break;   \
-    case 4: MICK_MA(LR, 4); break;   \
-    case 8: MICK_MA(LR, 8); break;   \
-    case 16: MICK_MA(LR, 16); break; \
-    case 24: MICK_MA(LR, 24); break; \
-    case 32: MICK_MA(LR, 32); break; \
+#define MICK_MA_A(LR)                                                   \
+  switch (modup_rows(G.alpha)) {                                        \
+    case 1: MICK_MA(LR, 1); break;                                      \
+    case 2: MICK_MA(LR, 2); break;                                      \
+    case 4: MICK_MA(LR, 4); break;                                      \
+    case 8: MICK_MA(LR, 8); break;                                      \
+    case 16: MICK_MA(LR, 16); break;                                    \
+    case 24: MICK_MA(LR, 24); break;                                    \
+    case 32: MICK_MA(LR, 32); break;                                    \
     default: return set_error(MICK_E_ARG, "digit width out of range"); \
   }
   if (prm->split_a == 7) {

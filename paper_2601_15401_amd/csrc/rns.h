@@ -16,6 +16,17 @@ inline int modup_rows(int alpha) {
   return r;
 }
 
+// The same-shape ModUp launch converts into two targets per workgroup for
+// digits of 5 to 8 primes (one source load feeds both); wider digits leave
+// no registers for a second target, and narrower ones read too few source
+// rows to gain.
+inline bool modup_two_targets(int alpha) { return modup_rows(alpha) == 8; }
+
+// Workgroups per source tile of the two-target kernel: ceil(level / 2) +
+// ceil(K / 2), an upper bound on the pairs of q targets plus the pairs of
+// special primes.
+__host__ __device__ inline int modup_pairs(int level, int E) { return (level + 1) / 2 + (E - level + 1) / 2; }
+
 struct CtPtrs {
   const uint32_t* p[kMaxK];
 };
