@@ -17,11 +17,12 @@ from paper_2601_15401_amd import mick
 pytestmark = pytest.mark.gpu
 
 # (log_n, L, K, dnum, seed, k_max): digit widths 7 (L=14, dnum=2), 5 (L=10,
-# dnum=2) and 8 (L=16, dnum=2); K odd and even
+# dnum=2) and 8 (L=16, dnum=2; L=8, dnum=1); K odd and even, down to 1
 SETS = {
     "L14K3d2": (13, 14, 3, 2, 51, 4),
     "L10K5d2": (13, 10, 5, 2, 52, 3),
     "L16K2d2": (13, 16, 2, 2, 53, 3),
+    "L8K1d1": (13, 8, 1, 1, 54, 3),
 }
 _cache = {}
 
@@ -71,6 +72,10 @@ def test_sets_take_the_two_target_kernel():
     ("L10K5d2", 2, 6),    # ragged: 5 and 1 primes
     ("L16K2d2", 3, 16),   # digits of 8, even counts
     ("L16K2d2", 2, 9),
+    ("L16K2d2", 2, 2),    # one digit holds every active q limb: no q targets
+    ("L14K3d2", 2, 3),    # no q targets, three special primes (one alone)
+    ("L8K1d1", 3, 8),     # a single special prime: its pair has one member
+    ("L8K1d1", 2, 5),
 ])
 def test_multiply_parity(name, k, level):
     c = ctx(name)
