@@ -94,6 +94,12 @@ def site_work(site, N, k, level, K, alpha, jobs):
     if site == "tensor":
         n_in, n_out = jobs * k * 2 * level, jobs * (k + 1) * level
         return limb * (n_in + n_out), jobs * level * N * (k * (k + 1) - 2) * 7.0
+    if site == "tensor_inttB":
+        # the tensor product, then pass B of d_2..d_k's INTT on the tile in
+        # LDS: the pass's output is written, nothing is read back
+        tb, tops = site_work("tensor", N, k, level, K, alpha, jobs)
+        n = jobs * (k - 1) * level
+        return tb + limb * n, tops + n * (N / 2) * stages_b * bfly
     if site == "moddown_rescale":
         return limb * jobs * (2 * E + 2 * (level - mu)), jobs * 2 * (level - mu) * N * (2 * (K + mu) + 30.0)
     return 0.0, 0.0

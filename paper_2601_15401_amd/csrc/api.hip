@@ -35,7 +35,7 @@ namespace {
 const char* const kSiteNames[P_COUNT] = {
     "tensor",       "intt_d.passA",  "intt_d.passB",  "modup_bconv_passA", "unused.passA", "unused.passB",
     "passB_kip",    "intt_acc.passA", "intt_acc.passB", "moddown_rescale", "ntt_out.passA", "ntt_out.passB",
-    "rescale_sums", "rescale_combine", "ntt_other.passA", "ntt_other.passB"};
+    "rescale_sums", "rescale_combine", "ntt_other.passA", "ntt_other.passB", "tensor_inttB"};
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 uint32_t g_prof_mask = ~0u;  // sites that record while profiling is on
@@ -355,17 +355,22 @@ int check_mul(const mick_params* prm, const mick_keys* keys, int k, int level) {
 }
 
 // Relinearisation and rescale of jobs whose tensor products are already in
-// the workspace (D at the start of each job block).
+// the workspace (D at the start of each job block).  d_pass_b: the first pass
+// of d_2..d_k's INTT has run too (k_tensor_ib), its output in dcoef.
 int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int level, int mu, uint32_t* ws,
-                     size_t job_stride, int n_jobs, uint32_t* out, size_t out_job, hipStream_t s) {
+                     size_t job_stride, int n_jobs, uint32_t* out, size_t out_job, hipStream_t s,
+                     bool d_pass_b = false) {
   const Layout lay = mul_layout(prm, k, level);
   const int N = prm->N, L = prm->L, K = prm->K, E = level + K, B = digits_at(prm, level);
   // ModUp: INTT of d_2..d_k, each limb also multiplied by its qhat_j^-1
   LimbMap m = simple_map(prm, 0, level);
   m.job_stride = (long long)job_stride;
   m.nfix_pos = prm->d_dscale + prm->dscale_off[level];
-  MICK_TRY(ntt_launch(prm, ws + lay.D + 2 * (size_t)level * N, ws + lay.dcoef, m, (k - 1) * level, n_jobs, true, s,
-                      P_INTT_D));
+  if (d_pass_b)
+    MICK_TRY(intt_pass_a_launch(prm, ws + lay.dcoef, m, (k - 1) * level, n_jobs, s, P_INTT_D));
+  else
+    MICK_TRY(ntt_launch(prm, ws + lay.D + 2 * (size_t)level * N, ws + lay.dcoef, m, (k - 1) * level, n_jobs, true, s,
+                        P_INTT_D));
   // basis conversion from each digit fused with pass A of the new limbs' NTT
   ModupArgs ma{};
   ma.tab = prm->d_modup;
@@ -935,8 +940,12 @@ int mick_mul_relin_rescale(const mick_params* prm, const mick_keys* keys, const 
     if (!cts_host[u]) return set_error(MICK_E_ARG, "NULL ciphertext pointer");
     in.p[u] = cts_host[u];
   }
-  MICK_TRY(launch_tensor(prm, in, 0, k, level, w + lay.D, 0, 1, s));
-  return relin_rescale_ws(prm, keys, k, level, k - 1, w, lay.total, 1, ct_out_dev, 0, s);
+  const bool fuse = tensor_takes_pass_b(k);
+  if (fuse)
+    MICK_TRY(launch_tensor_ib(prm, in, 0, k, level, w, 0, (long long)lay.D, (long long)lay.dcoef, 1, s));
+  else
+    MICK_TRY(launch_tensor(prm, in, 0, k, level, w + lay.D, 0, 1, s));
+  return relin_rescale_ws(prm, keys, k, level, k - 1, w, lay.total, 1, ct_out_dev, 0, s, fuse);
 }
 
 size_t mick_batch_workspace_bytes(const mick_params* prm, int n_jobs, int k, int level) {
@@ -957,9 +966,14 @@ int mick_mul_relin_rescale_batch(const mick_params* prm, const mick_keys* keys, 
   CtPtrs in{};
   const size_t ct_elems = 2 * (size_t)level * N;
   for (int u = 0; u < k; u++) in.p[u] = cts_dev + (size_t)u * ct_elems;
-  MICK_TRY(launch_tensor(prm, in, (long long)(k * ct_elems), k, level, w + lay.D, (long long)lay.total, n_jobs, s));
+  const bool fuse = tensor_takes_pass_b(k);
+  if (fuse)
+    MICK_TRY(launch_tensor_ib(prm, in, (long long)(k * ct_elems), k, level, w, (long long)lay.total,
+                              (long long)lay.D, (long long)lay.dcoef, n_jobs, s));
+  else
+    MICK_TRY(launch_tensor(prm, in, (long long)(k * ct_elems), k, level, w + lay.D, (long long)lay.total, n_jobs, s));
   const size_t out_job = 2 * (size_t)(level - k + 1) * N;
-  return relin_rescale_ws(prm, keys, k, level, k - 1, w, lay.total, n_jobs, outs_dev, out_job, s);
+  return relin_rescale_ws(prm, keys, k, level, k - 1, w, lay.total, n_jobs, outs_dev, out_job, s, fuse);
 }
 
 int mick_profile_enable(int on) {

@@ -194,6 +194,7 @@ enum ProfSite {
   P_RS_COMBINE,
   P_OTHER,
   P_OTHER_B,
+  P_TENSOR_IB,
   P_COUNT
 };
 

@@ -965,6 +965,98 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
     kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, T.red[pe], tw, itw);
 }
 
+// ------------------------------------------------------------------ tensor product + pass B of d_2..d_k's INTT
+
+// One 1024-element tile of one limb of every d_t: the tensor product (four
+// residues per thread, tensor4), all k + 1 limbs written as by k_tensor
+// (d_0, d_1 and the digits' own d_t limbs are read in the NTT domain later),
+// and d_2..d_k also kept in LDS, where the first pass of their inverse
+// transform (pass B: both of its rounds, twiddles staged once for the k - 1
+// limbs) runs before its output is written.  The pass then reads nothing
+// back from HBM.
+constexpr int kTibTileLog = 10;
+
+template <int LOGR, int K>
+constexpr int tib_lds_words() {
+  return (K - 1) * Geo<LOGR, kTibTileLog>::LDS_WORDS;
+}
+
+template <int LOGR, int K, bool LAZY>
+__device__ __forceinline__ void tensor_ib_body(const uint4 (&P)[K + 1], uint32_t* dc, size_t tpoly, uint32_t* lds,
+                                               const uint2* ltw, int s0, int col0, uint32_t q) {
+  using G = Geo<LOGR, kTibTileLog>;
+  using R1 = Rnd<LOGR, true, false, kThreads, kTibTileLog>;  // inverse: consecutive round first
+  using R2 = Rnd<LOGR, true, true, kThreads, kTibTileLog>;
+  const uint4 nf{};
+  // residues 4 tid .. 4 tid + 3 of the tile: one 2^LOGR-element block
+  const int e = 4 * (int)threadIdx.x;
+  const int c = e >> LOGR, r = e & ((1 << LOGR) - 1);
+#pragma unroll
+  for (int t = 2; t <= K; t++) {
+    uint32_t* tl = lds + (t - 2) * G::LDS_WORDS + c;
+    tl[r * G::PAD] = P[t].x;
+    tl[(r + 1) * G::PAD] = P[t].y;
+    tl[(r + 2) * G::PAD] = P[t].z;
+    tl[(r + 3) * G::PAD] = P[t].w;
+  }
+  __syncthreads();  // d_t tiles and staged twiddles
+  for (int it = threadIdx.x; it < (K - 1) * R1::ITEMS; it += kThreads) {
+    const int tt = it / R1::ITEMS;
+    int cc, rb, hi;
+    R1::decode(it - tt * R1::ITEMS, cc, rb, hi);
+    uint32_t x[R1::E];
+    load_lds<R1, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
+    item_bfly_t<R1::RB, false, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, cc}, s0 + R1::SL0, hi, q, nf);
+    store_lds<R1, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < (K - 1) * R2::ITEMS; it += kThreads) {
+    const int tt = it / R2::ITEMS;
+    int cc, rb, hi;
+    R2::decode(it - tt * R2::ITEMS, cc, rb, hi);
+    uint32_t x[R2::E];
+    load_lds<R2, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
+    item_bfly_t<R2::RB, false, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, cc}, s0 + R2::SL0, hi, q, nf);
+    store_global<R2>(x, dc + (size_t)tt * tpoly, 0, col0 + cc, rb);
+  }
+}
+
+// Grid: (N / 1024 tiles, level limbs, jobs).  ws: per job (stride ws_job),
+// D at d_off ([k+1][level][N]) and the pass-B outputs at dc_off
+// ([k-1][level][N]).
+template <int LOGR, int K>
+__global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_job_stride, int level, int log_n,
+                                                        uint32_t* ws, long long ws_job, long long d_off,
+                                                        long long dc_off, DevTables T) {
+  using G = Geo<LOGR, kTibTileLog>;
+  __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
+  __shared__ uint2 ltw[G::COLS * ((1 << LOGR) - 1)];
+  const int tile = blockIdx.x, j = blockIdx.y;
+  const size_t N = (size_t)1 << log_n;
+  const int s0 = log_n - LOGR;
+  const int col0 = tile * G::COLS;
+  const uint2* itw = reinterpret_cast<const uint2*>(T.itw) + ((size_t)j << log_n);
+  stage_tw_pass_b<G::COLS, LOGR, kThreads>(ltw, itw, s0, col0);
+  const size_t job_in = (size_t)blockIdx.z * (size_t)in_job_stride;
+  const uint32_t* inp[K];
+#pragma unroll
+  for (int u = 0; u < K; u++) inp[u] = in.p[u] + job_in;
+  const size_t n = (size_t)tile * kThreads + threadIdx.x;  // uint4 index: 1024 residues per tile
+  uint4 P[K + 1];
+  tensor4<K>(inp, level, log_n, j, n, T, P);
+  uint32_t* wsj = ws + (size_t)blockIdx.z * (size_t)ws_job;
+  uint32_t* D = wsj + d_off + (size_t)j * N;
+  const size_t tpoly = (size_t)level * N;
+#pragma unroll
+  for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(D + (size_t)t * tpoly)[n] = P[t];
+  uint32_t* dc = wsj + dc_off + (size_t)j * N;
+  const uint32_t q = T.mod[j];
+  if (q < (1u << 30))
+    tensor_ib_body<LOGR, K, true>(P, dc, tpoly, lds, ltw, s0, col0, q);
+  else
+    tensor_ib_body<LOGR, K, false>(P, dc, tpoly, lds, ltw, s0, col0, q);
+}
+
 // ------------------------------------------------------------------ job-table forms
 
 // One transform pass over the jobs of a table: stage S_INTT_D (d_2..d_k into
@@ -1189,6 +1281,40 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
 #undef MICK_MA
 #undef MICK_MA2
   return hip_error(hipGetLastError(), "modup launch");
+}
+
+int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,
+                     uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs, hipStream_t s) {
+  dim3 grid((unsigned)(prm->N >> kTibTileLog), (unsigned)level, (unsigned)n_jobs);
+  const DevTables& T = prm->dt;
+  const int ln = prm->log_n;
+  ProfScope ps(P_TENSOR_IB, s);
+#define MICK_TIB(LR, KK) \
+  k_tensor_ib<LR, KK><<<grid, kThreads, 0, s>>>(in, in_job_stride, level, ln, ws, ws_job, d_off, dc_off, T)
+#define MICK_TIB_K(LR)                                                   \
+  switch (k) {                                                           \
+    case 2: MICK_TIB(LR, 2); break;                                      \
+    case 3: MICK_TIB(LR, 3); break;                                      \
+    case 4: MICK_TIB(LR, 4); break;                                      \
+    case 5: MICK_TIB(LR, 5); break;                                      \
+    case 6: MICK_TIB(LR, 6); break;                                      \
+    case 7: MICK_TIB(LR, 7); break;                                      \
+    case 8: MICK_TIB(LR, 8); break;                                      \
+    case 9: MICK_TIB(LR, 9); break;                                      \
+    case 10: MICK_TIB(LR, 10); break;                                    \
+    case 11: MICK_TIB(LR, 11); break;                                    \
+    case 12: MICK_TIB(LR, 12); break;                                    \
+    default: return set_error(MICK_E_ARG, "k out of range");            \
+  }
+  switch (prm->split_b) {
+    case 6: MICK_TIB_K(6) break;
+    case 7: MICK_TIB_K(7) break;
+    case 8: MICK_TIB_K(8) break;
+    default: return set_error(MICK_E_ARG, "pass split out of range");
+  }
+#undef MICK_TIB_K
+#undef MICK_TIB
+  return hip_error(hipGetLastError(), "tensor + pass B launch");
 }
 
 int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,

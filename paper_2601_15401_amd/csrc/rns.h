@@ -31,6 +31,54 @@ struct CtPtrs {
   const uint32_t* p[kMaxK];
 };
 
+// eq. (d_u formula for n-ct mult): prod_u (c0^u + c1^u Y) = sum_t d_t Y^t for
+// four consecutive residues (uint4 index n) of limb j, built one factor at a
+// time.  Every partial product picks up one R^-1 per factor, removed at the
+// end by R^(K-1); P[t] = d_t, canonical.  The two products of canonical
+// residues in a step are summed exactly (below 2 m^2 < m 2^32) and reduced
+// once: the same residue, with the same factor R^-1, as two Montgomery
+// products and a modular add.
+template <int K>
+__device__ __forceinline__ void tensor4(const uint32_t* const (&inp)[K], int level, int log_n, int j, size_t n,
+                                        const DevTables& T, uint4 (&P)[K + 1]) {
+  const size_t N = (size_t)1 << log_n;
+  const uint32_t m = T.mod[j], minv = T.minv[j];
+  const size_t limb = (size_t)j * N;
+  const size_t poly = (size_t)level * N;
+  P[0] = reinterpret_cast<const uint4*>(inp[0] + limb)[n];
+  P[1] = reinterpret_cast<const uint4*>(inp[0] + poly + limb)[n];
+#pragma unroll
+  for (int u = 1; u < K; u++) {
+    const uint4 a = reinterpret_cast<const uint4*>(inp[u] + limb)[n];
+    const uint4 b = reinterpret_cast<const uint4*>(inp[u] + poly + limb)[n];
+    // new_t = P_t a + P_{t-1} b, t = u+1 .. 0 (descending keeps P_{t-1} intact)
+    P[u + 1].x = mont_mul(P[u].x, b.x, m, minv);
+    P[u + 1].y = mont_mul(P[u].y, b.y, m, minv);
+    P[u + 1].z = mont_mul(P[u].z, b.z, m, minv);
+    P[u + 1].w = mont_mul(P[u].w, b.w, m, minv);
+#pragma unroll
+    for (int t = u; t >= 1; t--) {
+      P[t].x = redc((uint64_t)P[t].x * a.x + (uint64_t)P[t - 1].x * b.x, m, minv);
+      P[t].y = redc((uint64_t)P[t].y * a.y + (uint64_t)P[t - 1].y * b.y, m, minv);
+      P[t].z = redc((uint64_t)P[t].z * a.z + (uint64_t)P[t - 1].z * b.z, m, minv);
+      P[t].w = redc((uint64_t)P[t].w * a.w + (uint64_t)P[t - 1].w * b.w, m, minv);
+    }
+    P[0].x = mont_mul(P[0].x, a.x, m, minv);
+    P[0].y = mont_mul(P[0].y, a.y, m, minv);
+    P[0].z = mont_mul(P[0].z, a.z, m, minv);
+    P[0].w = mont_mul(P[0].w, a.w, m, minv);
+  }
+  const uint32_t* rp = T.rpow + (size_t)j * 2 * (kMaxK + 1);
+  const uint32_t f = rp[2 * (K - 1)], fsh = rp[2 * (K - 1) + 1];
+#pragma unroll
+  for (int t = 0; t <= K; t++) {
+    P[t].x = shoup(P[t].x, f, fsh, m);
+    P[t].y = shoup(P[t].y, f, fsh, m);
+    P[t].z = shoup(P[t].z, f, fsh, m);
+    P[t].w = shoup(P[t].w, f, fsh, m);
+  }
+}
+
 struct ModupArgs {
   const uint32_t* tab;  // ModUp tables
   int tab_off[16];      // per digit offset of this level's table inside `tab`
@@ -64,6 +112,15 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
 // Pass B of those transforms fused with the key inner product, followed by
 // the first pass (pass B) of the accumulators' inverse transform; acc holds
 // that pass's output (ntt.hip).
+// Tensor product of n_jobs same-shape multiplies fused with pass B of the
+// INTT of d_2..d_k: D (all k + 1 polynomials) at ws + d_off and the pass-B
+// outputs at ws + dc_off, per job ws_job words apart.  Used from k = 5: the
+// pass's items then keep all 256 threads of a tile busy (at N = 2^16, k = 8,
+// batch 8: tensor 0.36 ms + pass B 0.29 ms -> 0.55 ms; at k = 3 half the
+// threads idle through the pass and the fused kernel gained nothing).
+inline bool tensor_takes_pass_b(int k) { return k >= 5; }
+int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,
+                     uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs, hipStream_t s);
 int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,
                  KipArgs A, hipStream_t s);
 int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out, const MdArgs& A, int mu, int n_jobs,

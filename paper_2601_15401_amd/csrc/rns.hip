@@ -19,55 +19,16 @@ __device__ __forceinline__ uint32_t mul_var(uint32_t a, uint32_t b, uint32_t m, 
 }
 
 // ------------------------------------------------------------------ tensor
-// eq. (d_u formula for n-ct mult): prod_u (c0^u + c1^u Y) = sum_t d_t Y^t,
-// built one factor at a time; every partial product picks up one R^-1 per
-// factor, removed at the end by R^(k-1).
+// The k + 1 limbs j of D at residues 4n .. 4n + 3 (tensor4).
 template <int K>
 __device__ __forceinline__ void tensor_body(const uint32_t* const (&inp)[K], int level, int log_n, uint32_t* D, int j,
                                             size_t n, const DevTables& T) {
-  const size_t N = (size_t)1 << log_n;
-  const uint32_t m = T.mod[j], minv = T.minv[j];
-  const size_t limb = (size_t)j * N;
-  const size_t poly = (size_t)level * N;
   uint4 P[K + 1];
-  P[0] = reinterpret_cast<const uint4*>(inp[0] + limb)[n];
-  P[1] = reinterpret_cast<const uint4*>(inp[0] + poly + limb)[n];
+  tensor4<K>(inp, level, log_n, j, n, T, P);
+  const size_t N = (size_t)1 << log_n;
+  uint32_t* out = D + (size_t)j * N;
 #pragma unroll
-  for (int u = 1; u < K; u++) {
-    const uint4 a = reinterpret_cast<const uint4*>(inp[u] + limb)[n];
-    const uint4 b = reinterpret_cast<const uint4*>(inp[u] + poly + limb)[n];
-    // new_t = P_t a + P_{t-1} b, t = u+1 .. 0 (descending keeps P_{t-1} intact).
-    // The two products of canonical residues are summed exactly (below
-    // 2 m^2 < m 2^32) and reduced once: the same residue, with the same
-    // factor R^-1, as two Montgomery products and a modular add.
-    P[u + 1].x = mont_mul(P[u].x, b.x, m, minv);
-    P[u + 1].y = mont_mul(P[u].y, b.y, m, minv);
-    P[u + 1].z = mont_mul(P[u].z, b.z, m, minv);
-    P[u + 1].w = mont_mul(P[u].w, b.w, m, minv);
-#pragma unroll
-    for (int t = u; t >= 1; t--) {
-      P[t].x = redc((uint64_t)P[t].x * a.x + (uint64_t)P[t - 1].x * b.x, m, minv);
-      P[t].y = redc((uint64_t)P[t].y * a.y + (uint64_t)P[t - 1].y * b.y, m, minv);
-      P[t].z = redc((uint64_t)P[t].z * a.z + (uint64_t)P[t - 1].z * b.z, m, minv);
-      P[t].w = redc((uint64_t)P[t].w * a.w + (uint64_t)P[t - 1].w * b.w, m, minv);
-    }
-    P[0].x = mont_mul(P[0].x, a.x, m, minv);
-    P[0].y = mont_mul(P[0].y, a.y, m, minv);
-    P[0].z = mont_mul(P[0].z, a.z, m, minv);
-    P[0].w = mont_mul(P[0].w, a.w, m, minv);
-  }
-  const uint32_t* rp = T.rpow + (size_t)j * 2 * (kMaxK + 1);
-  const uint32_t f = rp[2 * (K - 1)], fsh = rp[2 * (K - 1) + 1];
-  uint32_t* out = D + limb;
-#pragma unroll
-  for (int t = 0; t <= K; t++) {
-    uint4 v;
-    v.x = shoup(P[t].x, f, fsh, m);
-    v.y = shoup(P[t].y, f, fsh, m);
-    v.z = shoup(P[t].z, f, fsh, m);
-    v.w = shoup(P[t].w, f, fsh, m);
-    reinterpret_cast<uint4*>(out + (size_t)t * poly)[n] = v;
-  }
+  for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(out + (size_t)t * level * N)[n] = P[t];
 }
 
 template <int K>

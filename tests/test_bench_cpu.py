@@ -70,3 +70,13 @@ def test_source_hash_ignores_comments_and_whitespace():
     assert bench._code_tokens(a) == bench._code_tokens(b)
     assert bench._code_tokens(b) != bench._code_tokens(c)
     assert bench._code_tokens(b) != bench._code_tokens(d)  # literals are code
+
+
+def test_fused_tensor_site_is_the_tensor_plus_pass_b(monkeypatch):
+    _quiet(monkeypatch)
+    N, k, level, K, alpha, jobs = 1 << 16, 8, 32, 8, 8, 8
+    tb, tops = bench.site_work("tensor", N, k, level, K, alpha, jobs)
+    fb, fops = bench.site_work("tensor_inttB", N, k, level, K, alpha, jobs)
+    n = jobs * (k - 1) * level
+    assert fb == tb + 4.0 * N * n  # pass B's output written, nothing read back
+    assert fops == tops + n * (N / 2) * 8 * 9.0  # 8 of the 16 stages

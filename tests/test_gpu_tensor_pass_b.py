@@ -1,0 +1,73 @@
+"""GPU parity of the tensor product fused with pass B of the INTT of
+d_2..d_k (the multiply's first kernel from k = 5): pass-B blocks of 128
+(N = 2^14, 2^15) and 256 rows (N = 2^16), several k and levels, plain and
+batched launches, against the oracle bit for bit.  (64-row blocks, N = 2^13:
+the eight-prime set of test_gpu_parity multiplies k = 5 and 6.)  The unfused
+composition (plain tensor kernel, both INTT passes) runs on the same inputs
+against the oracle's textbook path.
+"""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import keys as okeys, mult, params as oparams
+from paper_2601_15401_amd import mick
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def ctx(log_n, k_max):
+    key = (log_n, k_max)
+    if key not in _cache:
+        op = oparams.preset(log_n)
+        seed = 70 + log_n
+        prm = mick.Params(log_n, op.L, op.K, op.dnum)
+        _cache[key] = (op, okeys.keygen(op, seed, k_max), prm, mick.Keys(prm, seed, k_max))
+    return _cache[key]
+
+
+def _rand_ct(rng, qs, n):
+    return np.stack([np.stack([rng.integers(0, q, n, dtype=np.int64).astype(np.uint64) for q in qs])
+                     for _ in range(2)])
+
+
+def _eq(got_t, want, what):
+    got = mick.to_numpy_u32(got_t).astype(np.uint64)
+    want = np.asarray(want, dtype=np.uint64)
+    assert got.shape == want.shape, (what, got.shape, want.shape)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, "%s: %d residues differ, first at %s" % (what, len(bad), bad[0].tolist())
+
+
+@pytest.mark.parametrize("log_n,k,level", [
+    (14, 5, 8), (14, 6, 7), (15, 5, 16), (15, 7, 11), (16, 5, 9), (16, 8, 10),
+])
+def test_fused_multiply_parity(log_n, k, level):
+    op, ok, prm, gk = ctx(log_n, 8)
+    rng = np.random.default_rng(zlib.crc32(b"tib-%d-%d-%d" % (log_n, k, level)))
+    cts = [_rand_ct(rng, op.q[:level], op.N) for _ in range(k)]
+    dev = [mick.from_numpy_u32(x) for x in cts]
+    out = mick.mul_relin_rescale(prm, gk, dev, level)
+    _eq(out, mult.mul_relin_rescale(op, ok, cts, level), "N=2^%d k=%d level=%d" % (log_n, k, level))
+    # the unfused composition (plain tensor kernel, both INTT passes, the
+    # textbook order) on the same inputs
+    d = mick.mul_k(prm, dev, level)
+    y = mick.relin_k(prm, gk, d, k, level)
+    _eq(mick.rescale_multi(prm, y, level, k - 1), mult.mul_relin_rescale(op, ok, cts, level, path="textbook"),
+        "unfused N=2^%d k=%d level=%d" % (log_n, k, level))
+
+
+@pytest.mark.parametrize("log_n,k,level,jobs", [(14, 6, 8, 3), (16, 5, 6, 2)])
+def test_fused_batch_matches_plain(log_n, k, level, jobs):
+    op, ok, prm, gk = ctx(log_n, 8)
+    rng = np.random.default_rng(zlib.crc32(b"tib-batch-%d-%d" % (log_n, k)))
+    host = [[_rand_ct(rng, op.q[:level], op.N) for _ in range(k)] for _ in range(jobs)]
+    batch = torch.stack([torch.stack([mick.from_numpy_u32(x) for x in h]) for h in host])
+    out = mick.mul_relin_rescale_batch(prm, gk, batch, level)
+    for j in range(jobs):
+        assert torch.equal(out[j], mick.mul_relin_rescale(prm, gk, [batch[j, u] for u in range(k)], level)), j
+    _eq(out[0], mult.mul_relin_rescale(op, ok, host[0], level), "batched job 0")
