@@ -967,39 +967,29 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
 
 // ------------------------------------------------------------------ tensor product + pass B of d_2..d_k's INTT
 
-// One 1024-element tile of one limb of every d_t: the tensor product (four
-// residues per thread, tensor4), all k + 1 limbs written as by k_tensor
-// (d_0, d_1 and the digits' own d_t limbs are read in the NTT domain later),
-// and d_2..d_k also kept in LDS, where the first pass of their inverse
-// transform (pass B: both of its rounds, twiddles staged once for the k - 1
-// limbs) runs before its output is written.  The pass then reads nothing
-// back from HBM.
-constexpr int kTibTileLog = 10;
+// One tile of one limb of every d_t: the tensor product (four residues per
+// thread and step, tensor4), all k + 1 limbs written as by k_tensor (d_0,
+// d_1 and the digits' own d_t limbs are read in the NTT domain later), and
+// d_2..d_k also kept in LDS, where the first pass of their inverse transform
+// (pass B: both of its rounds, twiddles staged once for the k - 1 limbs)
+// runs before its output is written.  The pass then reads nothing back from
+// HBM.  Tiles of 1024 residues from k = 5; 2048 for k = 3, 4 and 4096 for
+// k = 2, so that the k - 1 tiles' round items (64 per 1024 residues at 256
+// rows per block) still cover the 256 threads.
+__host__ __device__ constexpr int tib_tile_log(int k) { return k >= 5 ? 10 : (k >= 3 ? 11 : 12); }
 
 template <int LOGR, int K>
 constexpr int tib_lds_words() {
-  return (K - 1) * Geo<LOGR, kTibTileLog>::LDS_WORDS;
+  return (K - 1) * Geo<LOGR, tib_tile_log(K)>::LDS_WORDS;
 }
 
-template <int LOGR, int K, bool LAZY>
-__device__ __forceinline__ void tensor_ib_body(const uint4 (&P)[K + 1], uint32_t* dc, size_t tpoly, uint32_t* lds,
-                                               const uint2* ltw, int s0, int col0, uint32_t q) {
-  using G = Geo<LOGR, kTibTileLog>;
-  using R1 = Rnd<LOGR, true, false, kThreads, kTibTileLog>;  // inverse: consecutive round first
-  using R2 = Rnd<LOGR, true, true, kThreads, kTibTileLog>;
+template <int LOGR, int K, int TL, bool LAZY>
+__device__ __forceinline__ void tib_rounds(uint32_t* dc, size_t tpoly, uint32_t* lds, const uint2* ltw, int s0,
+                                           int col0, uint32_t q) {
+  using G = Geo<LOGR, TL>;
+  using R1 = Rnd<LOGR, true, false, kThreads, TL>;  // inverse: consecutive round first
+  using R2 = Rnd<LOGR, true, true, kThreads, TL>;
   const uint4 nf{};
-  // residues 4 tid .. 4 tid + 3 of the tile: one 2^LOGR-element block
-  const int e = 4 * (int)threadIdx.x;
-  const int c = e >> LOGR, r = e & ((1 << LOGR) - 1);
-#pragma unroll
-  for (int t = 2; t <= K; t++) {
-    uint32_t* tl = lds + (t - 2) * G::LDS_WORDS + c;
-    tl[r * G::PAD] = P[t].x;
-    tl[(r + 1) * G::PAD] = P[t].y;
-    tl[(r + 2) * G::PAD] = P[t].z;
-    tl[(r + 3) * G::PAD] = P[t].w;
-  }
-  __syncthreads();  // d_t tiles and staged twiddles
   for (int it = threadIdx.x; it < (K - 1) * R1::ITEMS; it += kThreads) {
     const int tt = it / R1::ITEMS;
     int cc, rb, hi;
@@ -1021,14 +1011,16 @@ __device__ __forceinline__ void tensor_ib_body(const uint4 (&P)[K + 1], uint32_t
   }
 }
 
-// Grid: (N / 1024 tiles, level limbs, jobs).  ws: per job (stride ws_job),
-// D at d_off ([k+1][level][N]) and the pass-B outputs at dc_off
-// ([k-1][level][N]).
+// Grid: (N / 2^tib_tile_log(K) tiles, level limbs, jobs).  ws: per job
+// (stride ws_job), D at d_off ([k+1][level][N]) and the pass-B outputs at
+// dc_off ([k-1][level][N]).
 template <int LOGR, int K>
 __global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_job_stride, int level, int log_n,
                                                         uint32_t* ws, long long ws_job, long long d_off,
                                                         long long dc_off, DevTables T) {
-  using G = Geo<LOGR, kTibTileLog>;
+  constexpr int TL = tib_tile_log(K);
+  constexpr int STEPS = 1 << (TL - 10);  // uint4 groups per thread
+  using G = Geo<LOGR, TL>;
   __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
   __shared__ uint2 ltw[G::COLS * ((1 << LOGR) - 1)];
   const int tile = blockIdx.x, j = blockIdx.y;
@@ -1041,20 +1033,35 @@ __global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_
   const uint32_t* inp[K];
 #pragma unroll
   for (int u = 0; u < K; u++) inp[u] = in.p[u] + job_in;
-  const size_t n = (size_t)tile * kThreads + threadIdx.x;  // uint4 index: 1024 residues per tile
-  uint4 P[K + 1];
-  tensor4<K>(inp, level, log_n, j, n, T, P);
   uint32_t* wsj = ws + (size_t)blockIdx.z * (size_t)ws_job;
   uint32_t* D = wsj + d_off + (size_t)j * N;
   const size_t tpoly = (size_t)level * N;
+  for (int g = 0; g < STEPS; g++) {
+    const int local = g * kThreads + threadIdx.x;  // uint4 index within the tile
+    const size_t n = (size_t)tile * (STEPS * kThreads) + local;
+    uint4 P[K + 1];
+    tensor4<K>(inp, level, log_n, j, n, T, P);
 #pragma unroll
-  for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(D + (size_t)t * tpoly)[n] = P[t];
+    for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(D + (size_t)t * tpoly)[n] = P[t];
+    // residues 4 local .. 4 local + 3: one 2^LOGR-residue block (column c)
+    const int e = 4 * local;
+    const int c = e >> LOGR, r = e & ((1 << LOGR) - 1);
+#pragma unroll
+    for (int t = 2; t <= K; t++) {
+      uint32_t* tl = lds + (t - 2) * G::LDS_WORDS + c;
+      tl[r * G::PAD] = P[t].x;
+      tl[(r + 1) * G::PAD] = P[t].y;
+      tl[(r + 2) * G::PAD] = P[t].z;
+      tl[(r + 3) * G::PAD] = P[t].w;
+    }
+  }
+  __syncthreads();  // d_t tiles and staged twiddles
   uint32_t* dc = wsj + dc_off + (size_t)j * N;
   const uint32_t q = T.mod[j];
   if (q < (1u << 30))
-    tensor_ib_body<LOGR, K, true>(P, dc, tpoly, lds, ltw, s0, col0, q);
+    tib_rounds<LOGR, K, TL, true>(dc, tpoly, lds, ltw, s0, col0, q);
   else
-    tensor_ib_body<LOGR, K, false>(P, dc, tpoly, lds, ltw, s0, col0, q);
+    tib_rounds<LOGR, K, TL, false>(dc, tpoly, lds, ltw, s0, col0, q);
 }
 
 // ------------------------------------------------------------------ job-table forms
@@ -1285,7 +1292,7 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
 
 int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,
                      uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs, hipStream_t s) {
-  dim3 grid((unsigned)(prm->N >> kTibTileLog), (unsigned)level, (unsigned)n_jobs);
+  dim3 grid((unsigned)(prm->N >> tib_tile_log(k)), (unsigned)level, (unsigned)n_jobs);
   const DevTables& T = prm->dt;
   const int ln = prm->log_n;
   ProfScope ps(P_TENSOR_IB, s);

@@ -114,11 +114,9 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
 // that pass's output (ntt.hip).
 // Tensor product of n_jobs same-shape multiplies fused with pass B of the
 // INTT of d_2..d_k: D (all k + 1 polynomials) at ws + d_off and the pass-B
-// outputs at ws + dc_off, per job ws_job words apart.  Used from k = 5: the
-// pass's items then keep all 256 threads of a tile busy (at N = 2^16, k = 8,
-// batch 8: tensor 0.36 ms + pass B 0.29 ms -> 0.55 ms; at k = 3 half the
-// threads idle through the pass and the fused kernel gained nothing).
-inline bool tensor_takes_pass_b(int k) { return k >= 5; }
+// outputs at ws + dc_off, per job ws_job words apart.  At N = 2^16, k = 8,
+// batch 8: tensor 0.36 ms + pass B 0.29 ms -> 0.55 ms.
+inline bool tensor_takes_pass_b(int k) { return k >= 2; }
 int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,
                      uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs, hipStream_t s);
 int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,
