@@ -1,8 +1,8 @@
 """GPU parity of the tensor product fused with pass B of the INTT of
-d_2..d_k (the multiply's first kernel from k = 5): pass-B blocks of 128
-(N = 2^14, 2^15) and 256 rows (N = 2^16), several k and levels, plain and
-batched launches, against the oracle bit for bit.  (64-row blocks, N = 2^13:
-the eight-prime set of test_gpu_parity multiplies k = 5 and 6.)  The unfused
+d_2..d_k (the fused multiply's first kernel): pass-B blocks of 64 (N = 2^13),
+128 (N = 2^14, 2^15) and 256 rows (N = 2^16), k from 5 to 12 (1024-residue
+tiles; k <= 4 takes larger tiles and runs in every other multiply test),
+plain and batched launches, against the oracle bit for bit.  The unfused
 composition (plain tensor kernel, both INTT passes) runs on the same inputs
 against the oracle's textbook path.
 """
@@ -71,3 +71,24 @@ def test_fused_batch_matches_plain(log_n, k, level, jobs):
     for j in range(jobs):
         assert torch.equal(out[j], mick.mul_relin_rescale(prm, gk, [batch[j, u] for u in range(k)], level)), j
     _eq(out[0], mult.mul_relin_rescale(op, ok, host[0], level), "batched job 0")
+
+
+_wide = {}
+
+
+@pytest.mark.parametrize("log_n,L,K,dnum,k,level", [
+    (13, 12, 3, 3, 12, 12),  # 64-row pass-B blocks, eleven d_t tiles in LDS
+    (13, 12, 3, 3, 9, 10),
+    (14, 12, 2, 4, 10, 11),  # 128-row blocks
+])
+def test_fused_wide_k_parity(log_n, L, K, dnum, k, level):
+    key = (log_n, L, K, dnum)
+    if key not in _wide:
+        op = oparams.make_params(log_n, L, K, dnum)
+        prm = mick.Params(log_n, L, K, dnum)
+        _wide[key] = (op, okeys.keygen(op, 90 + log_n, 12), prm, mick.Keys(prm, 90 + log_n, 12))
+    op, ok, prm, gk = _wide[key]
+    rng = np.random.default_rng(zlib.crc32(b"tib-wide-%d-%d-%d" % (log_n, k, level)))
+    cts = [_rand_ct(rng, op.q[:level], op.N) for _ in range(k)]
+    out = mick.mul_relin_rescale(prm, gk, [mick.from_numpy_u32(x) for x in cts], level)
+    _eq(out, mult.mul_relin_rescale(op, ok, cts, level), "N=2^%d k=%d level=%d" % (log_n, k, level))
