@@ -1044,7 +1044,8 @@ void job_blocks(const mick_params* prm, int k, int level, int (&nb)[kStages]) {
   auto pad8 = [](int x) { return (x + 7) / 8 * 8; };
   nb[S_TENSOR] = pad8((prm->N / 1024) * level);
   nb[S_INTT_D] = pad8(tiles * (k - 1) * level);
-  nb[S_MODUP] = pad8((k - 1) * B * (1 << (prm->log_n - kModupTileLog))) * E;
+  nb[S_MODUP] = pad8((k - 1) * B * (1 << (prm->log_n - kModupTileLog))) *
+                (modup_two_targets(prm->alpha) ? modup_pairs(level, E) : E);
   nb[S_KIP] = pad8(E * (1 << (prm->log_n - kKipTileLog)));
   nb[S_INTT_ACC] = pad8(tiles * 2 * E);
   nb[S_MODDOWN] = pad8(2 * (prm->N / 256));

@@ -434,8 +434,8 @@ constexpr int kModupThreads = 1 << (kModupTileLog - 5);
 
 // Workgroup order: the targets of one source tile run back to back on one
 // XCD (block b goes to XCD b % 8), so the source tile is read from L2.
-// One target per workgroup, except for same-shape launches at digits of 5
-// to 8 primes, which take two (k_modup_a2).
+// One target per workgroup, except at digits of 5 to 8 primes, which take
+// two (k_modup_a2, k_modup_a2_jt).
 // The conversion constants carry a factor R = 2^32 (Montgomery form): the
 // sum of up to 8 products of a residue below 2^30 and a constant below m
 // stays below 2m 2^32, so one Montgomery reduction returns it mod m (wider
@@ -661,7 +661,7 @@ __device__ __forceinline__ void modup_a2_body(__amdgpu_buffer_rsrc_t src, int na
   }
 }
 
-// Digits of 5 to 8 primes, same-shape launches.  Target pairs of one source
+// Digits of 5 to 8 primes.  Target pairs of one source
 // tile: the digit's q targets (every q limb outside the digit) two by two,
 // then the special primes two by two, so both members of a pair take the
 // same lazy or canonical butterflies.  modup_pairs() pairs per unit is an
@@ -671,9 +671,7 @@ __device__ __forceinline__ void modup_a2_body(__amdgpu_buffer_rsrc_t src, int na
 // source row, the second target's converted values) and no scratch.  Per
 // eight-job launch at the eight-input shape: 1277 us for the one-target
 // kernel at four waves, 1085 us here; forced to four waves this kernel
-// spills and takes 1169 us.  The job-table launch keeps the one-target
-// kernel: a job-table copy of this one in the same module changed the
-// compiler's register allocation of this one and gave back half its gain.
+// spills and takes 1169 us.
 template <int LOGR, int ALPHA>
 __global__ __launch_bounds__(kModupThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_modup_a2(
     const uint32_t* dsc, uint32_t* X, ModupArgs A, DevTables T) {
@@ -1166,6 +1164,73 @@ __global__ __launch_bounds__(kModupThreads) void k_modup_a_jt(const JobDesc* jt,
     modup_a_body<LOGR, ALPHA, false>(src, na, cc, minv, dst, lds, ltwa, H, col0, q, tw);
 }
 
+// Job-table form of k_modup_a2 (digits of 5 to 8 primes).  Blocks per job:
+// ceil(units / 8) 8 modup_pairs(level, E).
+template <int LOGR, int ALPHA>
+__global__ __launch_bounds__(kModupThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_modup_a2_jt(
+    const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
+  __shared__ uint32_t lds[Geo<LOGR, kModupTileLog>::LDS_WORDS];
+  __shared__ uint2 ltw[2][1 << LOGR];
+  const int j = find_job(jt, nj, S_MODUP, blockIdx.x);
+  const int local = blockIdx.x - jt[j].blk0[S_MODUP];
+  const int log_n = G.log_n;
+  const int k = jt[j].k, level = jt[j].level;
+  const int E = level + G.K, B = (level + G.alpha - 1) / G.alpha;
+  const int tiles = 1 << (log_n - kModupTileLog);
+  const int units = (k - 1) * B * tiles;
+  const int pairs = modup_pairs(level, E);
+  const int xcd = local & 7, seq = local >> 3;
+  const int pr = seq % pairs;
+  const int unit = (seq / pairs) * 8 + xcd;
+  if (unit >= units) return;
+  const int tile = unit % tiles;
+  const int tb = unit / tiles;  // (t - 2) B + b
+  const int t2 = tb / B, b = tb - t2 * B;
+  const int lo = b * G.alpha;
+  const int na = min(G.alpha, level - lo);
+  const int nq = level - na;
+  const int qp = (nq + 1) / 2;
+  int e0, e1;
+  if (pr < qp) {
+    const int i0 = 2 * pr, i1 = i0 + 1;
+    e0 = i0 < lo ? i0 : i0 + na;
+    e1 = i1 < nq ? (i1 < lo ? i1 : i1 + na) : -1;
+  } else {
+    e0 = level + 2 * (pr - qp);
+    if (e0 >= E) return;
+    e1 = e0 + 1 < E ? e0 + 1 : -1;
+  }
+  const bool two = e1 >= 0;
+  const int f1 = two ? e1 : e0;
+  const int p0 = e0 < level ? e0 : G.L + (e0 - level);
+  const int p1 = f1 < level ? f1 : G.L + (f1 - level);
+  const uint32_t q0 = T.mod[p0], q1 = T.mod[p1];
+  const uint2* tw0 = reinterpret_cast<const uint2*>(T.tw) + ((size_t)p0 << log_n);
+  const uint2* tw1 = reinterpret_cast<const uint2*>(T.tw) + ((size_t)p1 << log_n);
+  const size_t N = (size_t)1 << log_n;
+  const WsLayout lay(k, level, G.K, G.alpha, log_n);
+  const uint32_t* C = G.modup_tab + G.modup_off[(level - 1) * G.dnum + b] + 2 * ALPHA;
+  const uint32_t* base = jt[j].ws + lay.dcoef + ((size_t)t2 * level + lo) * N;
+  const __amdgpu_buffer_rsrc_t src = buffer_rsrc(base, (uint32_t)(na * N * 4));
+  uint32_t c0[ALPHA], c1[ALPHA];
+#pragma unroll
+  for (int a = 0; a < ALPHA; a++) {
+    c0[a] = C[a * E + e0];
+    c1[a] = C[a * E + f1];
+  }
+  uint32_t* xj = jt[j].ws + lay.X + (size_t)tb * E * N;
+  uint32_t* dst0 = xj + (size_t)e0 * N;
+  uint32_t* dst1 = two ? xj + (size_t)e1 * N : nullptr;
+  const int H = log_n - LOGR;
+  const int col0 = tile * Geo<LOGR, kModupTileLog>::COLS;
+  if (q0 < (1u << 30) && q1 < (1u << 30))
+    modup_a2_body<LOGR, ALPHA, true>(src, na, c0, c1, T.minv[p0], T.minv[p1], dst0, dst1, lds, ltw[0], ltw[1], H,
+                                     col0, q0, q1, tw0, tw1);
+  else
+    modup_a2_body<LOGR, ALPHA, false>(src, na, c0, c1, T.minv[p0], T.minv[p1], dst0, dst1, lds, ltw[0], ltw[1], H,
+                                      col0, q0, q1, tw0, tw1);
+}
+
 // Pass B + key inner product over the jobs of a table.  Blocks per job:
 // ceil(E tiles / 8) 8.
 template <int LOGR>
@@ -1372,13 +1437,14 @@ int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blo
   if (blocks <= 0) return MICK_OK;
   ProfScope ps(P_MODUP, s);
   const DevTables& T = prm->dt;
+#define MICK_MA2(LR, AL) k_modup_a2_jt<LR, AL><<<blocks, kModupThreads, 0, s>>>(jt, nj, G, T)
 #define MICK_MA(LR, AL) k_modup_a_jt<LR, AL><<<blocks, kModupThreads, 0, s>>>(jt, nj, G, T)
 #define MICK_MA_A(LR)                                                   \
   switch (modup_rows(G.alpha)) {                                        \
     case 1: MICK_MA(LR, 1); break;                                      \
     case 2: MICK_MA(LR, 2); break;                                      \
     case 4: MICK_MA(LR, 4); break;                                      \
-    case 8: MICK_MA(LR, 8); break;                                      \
+    case 8: MICK_MA2(LR, 8); break;                                     \
     case 16: MICK_MA(LR, 16); break;                                    \
     case 24: MICK_MA(LR, 24); break;                                    \
     case 32: MICK_MA(LR, 32); break;                                    \
@@ -1391,6 +1457,7 @@ int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blo
   }
 #undef MICK_MA_A
 #undef MICK_MA
+#undef MICK_MA2
   return hip_error(hipGetLastError(), "modup launch");
 }
 

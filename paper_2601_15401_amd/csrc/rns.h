@@ -16,10 +16,9 @@ inline int modup_rows(int alpha) {
   return r;
 }
 
-// The same-shape ModUp launch converts into two targets per workgroup for
-// digits of 5 to 8 primes (one source load feeds both); wider digits leave
-// no registers for a second target, and narrower ones read too few source
-// rows to gain.
+// The ModUp kernels convert into two targets per workgroup for digits of 5
+// to 8 primes (one source load feeds both); wider digits leave no registers
+// for a second target, and narrower ones read too few source rows to gain.
 inline bool modup_two_targets(int alpha) { return modup_rows(alpha) == 8; }
 
 // Workgroups per source tile of the two-target kernel: ceil(level / 2) +

@@ -1,9 +1,8 @@
-"""GPU parity of the two-target ModUp kernel (same-shape launches at digits
-of 5 to 8 primes): target pairs that straddle the digit's own limbs, an odd
-number of q targets or of special primes (a pair with one member), ragged
-last digits and digits padded to eight rows, through the plain and batched
-launches against the oracle bit for bit, and against the job-table launch,
-which keeps the one-target kernel.
+"""GPU parity of the two-target ModUp kernels (digits of 5 to 8 primes):
+target pairs that straddle the digit's own limbs, an odd number of q
+targets or of special primes (a pair with one member), ragged last digits
+and digits padded to eight rows, through the plain, batched and job-table
+launches, against the oracle bit for bit.
 """
 import zlib
 
@@ -96,9 +95,8 @@ def test_relin_parity():
 
 
 def test_batched_and_job_table_match_plain():
-    """Same-shape batch and a job table mixing k and level (one-target
-    kernel): every job equals its plain multiply (two-target kernel); two
-    jobs are checked against the oracle."""
+    """Same-shape batch and a job table mixing k and level: every job equals
+    its plain multiply; two jobs are checked against the oracle."""
     c = ctx("L14K3d2")
     rng = np.random.default_rng(_seed("pair-batch"))
     k, level, jobs = 3, 12, 3
