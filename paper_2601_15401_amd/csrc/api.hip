@@ -1042,7 +1042,7 @@ void job_blocks(const mick_params* prm, int k, int level, int (&nb)[kStages]) {
   const int tiles = 1 << (prm->log_n - 13);
   const int E = level + prm->K, B = digits_at(prm, level);
   auto pad8 = [](int x) { return (x + 7) / 8 * 8; };
-  nb[S_TENSOR] = pad8((prm->N / 1024) * level);
+  nb[S_TENSOR] = pad8((prm->N >> tib_tile_log(k)) * level);  // k_tensor_ib_jt
   nb[S_INTT_D] = pad8(tiles * (k - 1) * level);
   nb[S_MODUP] = pad8((k - 1) * B * (1 << (prm->log_n - kModupTileLog))) *
                 (modup_two_targets(prm->alpha) ? modup_pairs(level, E) : E);
@@ -1232,7 +1232,7 @@ int mick_plan_execute(const mick_plan* plan, void* stream) {
   for (size_t i = 0; i < plan->runs.size(); i++) {
     const auto& r = plan->runs[i];
     const int j1 = i + 1 < plan->runs.size() ? plan->runs[i + 1].j0 : n;
-    MICK_TRY(launch_tensor_jt(prm, djt, r.j0, j1 - r.j0, r.k, r.tensor_blocks, s));
+    MICK_TRY(launch_tensor_ib_jt(prm, djt, r.j0, j1 - r.j0, r.k, r.tensor_blocks, s));
   }
   MICK_TRY(launch_ntt_jt(prm, djt, n, S_INTT_D, plan->blocks[S_INTT_D], G, s));
   MICK_TRY(launch_modup_a_jt(prm, djt, n, plan->blocks[S_MODUP], G, s));

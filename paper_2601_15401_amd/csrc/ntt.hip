@@ -974,8 +974,6 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
 // HBM.  Tiles of 1024 residues from k = 5; 2048 for k = 3, 4 and 4096 for
 // k = 2, so that the k - 1 tiles' round items (64 per 1024 residues at 256
 // rows per block) still cover the 256 threads.
-__host__ __device__ constexpr int tib_tile_log(int k) { return k >= 5 ? 10 : (k >= 3 ? 11 : 12); }
-
 template <int LOGR, int K>
 constexpr int tib_lds_words() {
   return (K - 1) * Geo<LOGR, tib_tile_log(K)>::LDS_WORDS;
@@ -1009,29 +1007,20 @@ __device__ __forceinline__ void tib_rounds(uint32_t* dc, size_t tpoly, uint32_t*
   }
 }
 
-// Grid: (N / 2^tib_tile_log(K) tiles, level limbs, jobs).  ws: per job
-// (stride ws_job), D at d_off ([k+1][level][N]) and the pass-B outputs at
-// dc_off ([k-1][level][N]).
+// One tile of limb j: inp the k inputs, wsj the job's workspace with D at
+// d_off ([k+1][level][N]) and the pass-B outputs at dc_off ([k-1][level][N]).
 template <int LOGR, int K>
-__global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_job_stride, int level, int log_n,
-                                                        uint32_t* ws, long long ws_job, long long d_off,
-                                                        long long dc_off, DevTables T) {
+__device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], int level, int log_n, int j,
+                                               int tile, uint32_t* wsj, size_t d_off, size_t dc_off,
+                                               const DevTables& T, uint32_t* lds, uint2* ltw) {
   constexpr int TL = tib_tile_log(K);
   constexpr int STEPS = 1 << (TL - 10);  // uint4 groups per thread
   using G = Geo<LOGR, TL>;
-  __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
-  __shared__ uint2 ltw[G::COLS * ((1 << LOGR) - 1)];
-  const int tile = blockIdx.x, j = blockIdx.y;
   const size_t N = (size_t)1 << log_n;
   const int s0 = log_n - LOGR;
   const int col0 = tile * G::COLS;
   const uint2* itw = reinterpret_cast<const uint2*>(T.itw) + ((size_t)j << log_n);
   stage_tw_pass_b<G::COLS, LOGR, kThreads>(ltw, itw, s0, col0);
-  const size_t job_in = (size_t)blockIdx.z * (size_t)in_job_stride;
-  const uint32_t* inp[K];
-#pragma unroll
-  for (int u = 0; u < K; u++) inp[u] = in.p[u] + job_in;
-  uint32_t* wsj = ws + (size_t)blockIdx.z * (size_t)ws_job;
   uint32_t* D = wsj + d_off + (size_t)j * N;
   const size_t tpoly = (size_t)level * N;
   for (int g = 0; g < STEPS; g++) {
@@ -1060,6 +1049,43 @@ __global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_
     tib_rounds<LOGR, K, TL, true>(dc, tpoly, lds, ltw, s0, col0, q);
   else
     tib_rounds<LOGR, K, TL, false>(dc, tpoly, lds, ltw, s0, col0, q);
+}
+
+// Grid: (N / 2^tib_tile_log(K) tiles, level limbs, jobs); per job ws_job
+// words of workspace.
+template <int LOGR, int K>
+__global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_job_stride, int level, int log_n,
+                                                        uint32_t* ws, long long ws_job, long long d_off,
+                                                        long long dc_off, DevTables T) {
+  __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
+  __shared__ uint2 ltw[Geo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
+  const size_t job_in = (size_t)blockIdx.z * (size_t)in_job_stride;
+  const uint32_t* inp[K];
+#pragma unroll
+  for (int u = 0; u < K; u++) inp[u] = in.p[u] + job_in;
+  tensor_ib_tile<LOGR, K>(inp, level, log_n, blockIdx.y, blockIdx.x, ws + (size_t)blockIdx.z * (size_t)ws_job,
+                          (size_t)d_off, (size_t)dc_off, T, lds, ltw);
+}
+
+// Job-table form: jobs [j0, j0 + nj) of equal k; blocks per job
+// (N / 2^tib_tile_log(k)) level.  D and the pass-B outputs at their places
+// in the job's workspace (WsLayout).
+template <int LOGR, int K>
+__global__ __launch_bounds__(kThreads) void k_tensor_ib_jt(const JobDesc* jt, int j0, int nj, int log_n,
+                                                           DevTables T) {
+  __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
+  __shared__ uint2 ltw[Geo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
+  const int j = j0 + find_job(jt + j0, nj, S_TENSOR, blockIdx.x);
+  const int local = blockIdx.x - jt[j].blk0[S_TENSOR];
+  const int tiles = 1 << (log_n - tib_tile_log(K));
+  const int level = jt[j].level;
+  if (local >= tiles * level) return;
+  const uint32_t* inp[K];
+#pragma unroll
+  for (int u = 0; u < K; u++) inp[u] = jt[j].in[u];
+  const size_t N = (size_t)1 << log_n;
+  tensor_ib_tile<LOGR, K>(inp, level, log_n, local / tiles, local % tiles, jt[j].ws, 0,
+                          (size_t)(K + 1) * level * N, T, lds, ltw);
 }
 
 // ------------------------------------------------------------------ job-table forms
@@ -1389,6 +1415,39 @@ int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_
   return hip_error(hipGetLastError(), "tensor + pass B launch");
 }
 
+int launch_tensor_ib_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks,
+                        hipStream_t s) {
+  if (blocks <= 0) return MICK_OK;
+  const DevTables& T = prm->dt;
+  const int ln = prm->log_n;
+  ProfScope ps(P_TENSOR_IB, s);
+#define MICK_TIB(LR, KK) k_tensor_ib_jt<LR, KK><<<blocks, kThreads, 0, s>>>(jt, j0, nj, ln, T)
+#define MICK_TIB_K(LR)                                                   \
+  switch (k) {                                                           \
+    case 2: MICK_TIB(LR, 2); break;                                      \
+    case 3: MICK_TIB(LR, 3); break;                                      \
+    case 4: MICK_TIB(LR, 4); break;                                      \
+    case 5: MICK_TIB(LR, 5); break;                                      \
+    case 6: MICK_TIB(LR, 6); break;                                      \
+    case 7: MICK_TIB(LR, 7); break;                                      \
+    case 8: MICK_TIB(LR, 8); break;                                      \
+    case 9: MICK_TIB(LR, 9); break;                                      \
+    case 10: MICK_TIB(LR, 10); break;                                    \
+    case 11: MICK_TIB(LR, 11); break;                                    \
+    case 12: MICK_TIB(LR, 12); break;                                    \
+    default: return set_error(MICK_E_ARG, "k out of range");            \
+  }
+  switch (prm->split_b) {
+    case 6: MICK_TIB_K(6) break;
+    case 7: MICK_TIB_K(7) break;
+    case 8: MICK_TIB_K(8) break;
+    default: return set_error(MICK_E_ARG, "pass split out of range");
+  }
+#undef MICK_TIB_K
+#undef MICK_TIB
+  return hip_error(hipGetLastError(), "tensor + pass B launch");
+}
+
 int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,
                  KipArgs A, hipStream_t s) {
   A.tiles = 1 << (prm->log_n - kKipTileLog);
@@ -1421,8 +1480,9 @@ int launch_ntt_jt(const mick_params* prm, const JobDesc* jt, int nj, int stage, 
     ProfScope ps(site + 1, s);
     launch_pass_jt<true, true>(lb, blocks, s, jt, nj, stage, G, prm->dt, la);
   } else {
-    // the accumulators' pass B ran inside the key-product kernel
-    if (stage != S_INTT_ACC) {
+    // pass B of the accumulators ran inside the key-product kernel, and that
+    // of d_2..d_k inside the tensor kernel
+    if (stage != S_INTT_ACC && stage != S_INTT_D) {
       ProfScope ps(site + 1, s);
       launch_pass_jt<false, true>(lb, blocks, s, jt, nj, stage, G, prm->dt, la);
     }

@@ -116,6 +116,17 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
 // outputs at ws + dc_off, per job ws_job words apart.  At N = 2^16, k = 8,
 // batch 8: tensor 0.36 ms + pass B 0.29 ms -> 0.55 ms.
 inline bool tensor_takes_pass_b(int k) { return k >= 2; }
+
+// Residues per tile of the fused kernel (log2): 1024 from k = 5; 2048 for
+// k = 3, 4 and 4096 for k = 2, so that the k - 1 tiles' pass-B items (64 per
+// 1024 residues at 256 rows per block) still cover a workgroup's 256 threads.
+__host__ __device__ constexpr int tib_tile_log(int k) { return k >= 5 ? 10 : (k >= 3 ? 11 : 12); }
+
+// Job-table form: jobs [j0, j0 + nj) of equal k, blocks as job_blocks counts
+// them; every job of a table takes it (the table's INTT of d_2..d_k then
+// runs its pass A only).
+int launch_tensor_ib_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks,
+                        hipStream_t s);
 int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,
                      uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs, hipStream_t s);
 int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,
@@ -124,7 +135,6 @@ int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out
                       hipStream_t s);
 // Job-table forms (heterogeneous batches): jobs [j0, j0 + nj) of the table,
 // all with the given k (mu = k - 1); `blocks` covers their block ranges.
-int launch_tensor_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks, hipStream_t s);
 int launch_moddown_rs_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int mu, int blocks,
                          const GroupConsts& G, hipStream_t s);
 int launch_ntt_jt(const mick_params* prm, const JobDesc* jt, int nj, int stage, int blocks, const GroupConsts& G,

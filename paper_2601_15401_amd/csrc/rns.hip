@@ -42,20 +42,6 @@ __global__ __launch_bounds__(kThreads) void k_tensor(CtPtrs in, long long in_job
                  (size_t)blockIdx.x * kThreads + threadIdx.x, T);
 }
 
-// Job-table form: jobs [j0, j0 + nj) of equal k; blocks per job (N / 1024) level.
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_tensor_jt(const JobDesc* jt, int j0, int nj, int log_n, DevTables T) {
-  const int j = j0 + find_job(jt + j0, nj, S_TENSOR, blockIdx.x);
-  const int local = blockIdx.x - jt[j].blk0[S_TENSOR];
-  const int xb = 1 << (log_n - 10);
-  const int level = jt[j].level;
-  if (local >= xb * level) return;
-  const uint32_t* inp[K];
-#pragma unroll
-  for (int u = 0; u < K; u++) inp[u] = jt[j].in[u];
-  tensor_body<K>(inp, level, log_n, jt[j].ws, local / xb, (size_t)(local % xb) * kThreads + threadIdx.x, T);
-}
-
 // ------------------------------------------------------------------ ModDown + multi-rescale
 // Input: acc after the INTT, coefficient domain: rows q_0..q_{l-1} hold
 // INTT(D + P^-1 C~) (eq. (moddown improved 2)), rows p_i hold INTT(C~^(p)).
@@ -421,21 +407,6 @@ int launch_moddown_rs(const mick_params* prm, const uint32_t* acc, uint32_t* out
     default: return set_error(MICK_E_ARG, "mu out of range for the fused rescale");
   }
   return hip_error(hipGetLastError(), "moddown launch");
-}
-
-int launch_tensor_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks, hipStream_t s) {
-  if (blocks <= 0) return MICK_OK;
-  const DevTables& T = prm->dt;
-  const int ln = prm->log_n;
-  ProfScope ps(P_TENSOR, s);
-  switch (k) {
-#define MICK_T(KK) \
-  case KK: k_tensor_jt<KK><<<blocks, kThreads, 0, s>>>(jt, j0, nj, ln, T); break;
-    MICK_T(2) MICK_T(3) MICK_T(4) MICK_T(5) MICK_T(6) MICK_T(7) MICK_T(8) MICK_T(9) MICK_T(10) MICK_T(11) MICK_T(12)
-#undef MICK_T
-    default: return set_error(MICK_E_ARG, "k out of range");
-  }
-  return hip_error(hipGetLastError(), "tensor launch");
 }
 
 int launch_moddown_rs_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int mu, int blocks,
