@@ -114,7 +114,10 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
 // Tensor product of n_jobs same-shape multiplies fused with pass B of the
 // INTT of d_2..d_k: D (all k + 1 polynomials) at ws + d_off and the pass-B
 // outputs at ws + dc_off, per job ws_job words apart.  At N = 2^16, k = 8,
-// batch 8: tensor 0.36 ms + pass B 0.29 ms -> 0.55 ms.
+// batch 8: tensor 0.36 ms + pass B 0.29 ms -> 0.55 ms.  Every k takes it
+// now (tile sizes by k, tib_tile_log); the predicate is the one switch
+// between it and the plain tensor launch + two-pass INTT in the fused
+// multiply.
 inline bool tensor_takes_pass_b(int k) { return k >= 2; }
 
 // Residues per tile of the fused kernel (log2): 1024 from k = 5; 2048 for
