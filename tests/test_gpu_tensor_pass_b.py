@@ -92,3 +92,31 @@ def test_fused_wide_k_parity(log_n, L, K, dnum, k, level):
     cts = [_rand_ct(rng, op.q[:level], op.N) for _ in range(k)]
     out = mick.mul_relin_rescale(prm, gk, [mick.from_numpy_u32(x) for x in cts], level)
     _eq(out, mult.mul_relin_rescale(op, ok, cts, level), "N=2^%d k=%d level=%d" % (log_n, k, level))
+
+
+def test_profiled_sites_of_the_fused_multiply():
+    """The launch sites bench.py prices: the fused tensor kernel reports as
+    tensor_inttB, the INTT of d_2..d_k as its pass A only; a selection keeps
+    the other sites out."""
+    op, ok, prm, gk = ctx(14, 8)
+    rng = np.random.default_rng(5)
+    k, level = 3, 8
+    dev = [mick.from_numpy_u32(_rand_ct(rng, op.q[:level], op.N)) for _ in range(k)]
+    mick.mul_relin_rescale(prm, gk, dev, level)  # warm
+    torch.cuda.synchronize()
+    mick.profile_enable(True)
+    try:
+        mick.profile_collect()
+        mick.mul_relin_rescale(prm, gk, dev, level)
+        sites = mick.profile_collect()
+        mick.profile_select(["tensor_inttB"])
+        mick.mul_relin_rescale(prm, gk, dev, level)
+        only = mick.profile_collect()
+    finally:
+        mick.profile_select(None)
+        mick.profile_enable(False)
+    for s in ("tensor_inttB", "intt_d.passA", "modup_bconv_passA", "passB_kip", "intt_acc.passA",
+              "moddown_rescale", "ntt_out.passA", "ntt_out.passB"):
+        assert s in sites and sites[s][1] == 1, (s, sites)
+    assert "tensor" not in sites and "intt_d.passB" not in sites, sites
+    assert set(only) == {"tensor_inttB"}, only
