@@ -97,6 +97,75 @@ def test_splitmix64_known_answers():
     assert [int(v) for v in prng.draws(0, 3)] == want
 
 
+# Known-answer vectors for the sampler conventions written in the library
+# header (stream keys, ternary selection, slot values), worked by hand from
+# that text and the published SplitMix64 outputs of state 0:
+#   s_1..s_8 = e220a8397b1dcdaf 6e789e6aa1b965f4 06c45d188009454f
+#              f88bb8a8724c81ec 1b39896a51a8749b 53cb9f0c747ea2ea
+#              2c829abe1f4532e1 c584133ac916ab3c
+# (s_n = mix64(n G), G = 0x9E3779B97F4A7C15), so that a misreading shared by
+# the oracle and the library's host samplers fails here.
+PUB = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC,
+       0x1B39896A51A8749B, 0x53CB9F0C747EA2EA, 0x2C829ABE1F4532E1, 0xC584133AC916AB3C]
+
+
+def test_splitmix64_published_sequence():
+    assert [prng.draw(0, n) for n in range(8)] == PUB
+
+
+def test_stream_key_chain_known_answer():
+    """h = mix64(seed + G), then h = mix64((h ^ w) + G) for w = tag, a, b, c.
+    With seed = -G the first step is mix64(0) = 0; the empty tag packs to 0,
+    so the second step is mix64(G) = s_1; a = s_1 ^ G makes the third
+    mix64(2G) = s_2, b = s_2 ^ 2G the fourth s_3, c = s_3 ^ 3G the last s_4.
+    Any other order of the words, an add in place of the xor, or a missing
+    seed offset breaks the chain."""
+    G, M = prng.GAMMA, (1 << 64) - 1
+    a = PUB[0] ^ G
+    b = PUB[1] ^ ((2 * G) & M)
+    c = PUB[2] ^ ((3 * G) & M)
+    assert (a, b, c) == (0x7C17D1800457B1BA, 0x52166D185F2D9DDE, 0xDC623034FDD63170)
+    assert prng.stream_key((-G) & M, "", a, b, c) == PUB[3]
+    # the tag's ASCII bytes little-endian: "SK" = 0x53 'S', 0x4B 'K'
+    assert prng.tag("SK") == 0x4B53 and prng.tag("EVK_A") == 0x415F4B5645
+    # a non-empty tag: h after the tag step is mix64(0x4B53 + G); a = h ^ G
+    # steers the next step onto 2G, and the chain again ends on s_4
+    h_tag = prng.mix64(0x4B53 + G)
+    assert prng.stream_key((-G) & M, "SK", h_tag ^ G, b, c) == PUB[3]
+
+
+def test_ternary_selection_known_answer():
+    """Partial Fisher-Yates of the header: step i takes j = i + draw(2i) mod
+    (N - i), swaps positions i and j, sign + iff draw(2i + 1) is even.
+    Key 0 (draw n = s_{n+1}), N = 4, h = 2:
+      i = 0: s_1 = ..af, 0xaf mod 4 = 3, j = 3, order [3,1,2,0]; s_2 = ..f4
+             even: position 3 gets +1;
+      i = 1: s_3 mod 3 = (hex digit sum 94) mod 3 = 1, j = 2, order
+             [3,2,1,0]; s_4 = ..ec even: position 2 gets +1.
+    h = 3 adds i = 2: s_5 = ..9b odd, mod 2 = 1, j = 3, order [3,2,0,1];
+      s_6 = ..ea even: position 0 gets +1.
+    Key G (draw n = s_{n+2}), N = 4, h = 2:
+      i = 0: s_2 = ..f4, mod 4 = 0, j = 0; s_3 = ..4f odd: position 0 gets -1;
+      i = 1: s_4 mod 3 = (hex digit sum 139) mod 3 = 1, j = 2, order
+             [0,2,1,3]; s_5 = ..9b odd: position 2 gets -1."""
+    assert prng.ternary_hw(0, 4, 2).tolist() == [0, 0, 1, 1]
+    assert prng.ternary_hw(0, 4, 3).tolist() == [1, 0, 1, 1]
+    assert prng.ternary_hw(prng.GAMMA, 4, 2).tolist() == [-1, 0, -1, 0]
+
+
+def test_slot_values_known_answer():
+    """re_j from draw 2j, im_j from draw 2j + 1, each 2 (u >> 11) 2^-53 - 1.
+    Key 0: s_1 >> 11 = 0x1c4415072f63b9, doubled 0x38882a0e5ec772, minus 2^53
+    = 0x18882a0e5ec772, i.e. re_0 = 0x1.8882a0e5ec772p-1;
+    s_2 >> 11 = 0xdcf13cd54372c, doubled 0x1b9e279aa86e58, minus 2^53 =
+    -0x461d8655791a8, i.e. im_0 = -0x1.18761955e46a0p-3."""
+    re, im = prng.slots(0, 2)
+    assert re[0] == float.fromhex("0x1.8882a0e5ec772p-1")
+    assert im[0] == float.fromhex("-0x1.18761955e46a0p-3")
+    assert (PUB[2] >> 11) * 2 - (1 << 53) == int(re[1] * 2.0 ** 53)
+    assert (PUB[3] >> 11) * 2 - (1 << 53) == int(im[1] * 2.0 ** 53)
+
+
 def test_stream_keys_distinct_and_deterministic():
     ks = {prng.stream_key(1, "EVK_A", t, b, i) for t in range(2, 5) for b in range(4) for i in range(8)}
     assert len(ks) == 3 * 4 * 8
