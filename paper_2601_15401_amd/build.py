@@ -1,14 +1,17 @@
-"""Builds libmick.so in the package directory with hipcc for gfx950."""
+"""Builds libmick.so and the mick_rates probe in the package directory with
+hipcc for gfx950.  Translation units compile in parallel."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmick.so")
+RATES = os.path.join(PKG, "mick_rates")
 HIP_SOURCES = ["ntt.hip", "rns.hip", "api.hip", "queue.hip", "tree.hip"]
 HOST_SOURCES = ["host_math.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -25,23 +28,33 @@ def _run(cmd):
     return out
 
 
+def _jobs() -> int:
+    return max(1, min(8, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+
+
 def build(verbose: bool = False) -> str:
     obj_dir = os.path.join(ROOT, "_build")
     os.makedirs(obj_dir, exist_ok=True)
+    steps = []
     objs = []
     for src in HIP_SOURCES:
         o = os.path.join(obj_dir, src + ".o")
-        _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
+        steps.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
     for src in HOST_SOURCES:
         o = os.path.join(obj_dir, src + ".o")
-        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", o])
+        steps.append(["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
+    rates_tmp = RATES + ".tmp"
+    steps.append([HIPCC] + HIP_FLAGS + [os.path.join(CSRC, "rates.hip"), "-o", rates_tmp])
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        list(ex.map(_run, steps))
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp])
     os.replace(tmp, LIB)
+    os.replace(rates_tmp, RATES)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", RATES)
     return LIB
 
 
