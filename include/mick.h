@@ -67,7 +67,11 @@ enum {
   MICK_E_NOMEM = -4,  /* device or host allocation failed */
   MICK_E_HIP = -5,    /* a HIP runtime call failed (detail in mick_last_error) */
   MICK_E_RANGE = -6,  /* a decrypted coefficient does not fit the output type */
-  MICK_E_WS = -7      /* workspace smaller than mick_workspace_bytes() */
+  MICK_E_WS = -7,     /* workspace smaller than mick_workspace_bytes() */
+  MICK_E_BUSY = -8,   /* a queued job's workspace exceeds the queue's memory budget,
+                         or a job asked to be cancelled is already running */
+  MICK_E_CANCELLED = -9, /* per-job status: removed from a queue by mick_queue_cancel */
+  MICK_PENDING = 1    /* per-job status only: accepted by a queue, not yet complete */
 };
 
 typedef struct mick_params mick_params;
@@ -88,6 +92,13 @@ const char* mick_last_error(void);
  * immutable and may be shared by threads and streams; free it with
  * mick_params_destroy (NULL-safe) after all work using it has completed. */
 int mick_params_create(int log_n, int L, int K, int dnum, mick_params** out);
+/* The scale of a multiply's output (Sec. II rescaling: each rescale divides
+ * the scale by the dropped prime): prod_u scales_host[u] over
+ * prod q_{level-k+1} .. q_{level-1}, the k - 1 primes the multiply drops at
+ * `level`.  The library tracks no scale of its own: the ring arithmetic of
+ * the multiply does not depend on it, so it is the caller's (Sec. V-B, the
+ * scale after mu rescales of a product of k ciphertexts).  Host only. */
+int mick_output_scale(const mick_params* prm, const double* scales_host, int k, int level, double* out_host);
 void mick_params_destroy(mick_params* prm);
 /* Host copies of q_0..q_{L-1} (L values) and p_0..p_{K-1} (K values). */
 int mick_params_moduli(const mick_params* prm, uint32_t* q_host, uint32_t* p_host);
@@ -199,10 +210,13 @@ typedef struct mick_job {
   int level;                 /* k..L */
   const uint32_t* cts[12];   /* k device pointers, uint32[2][level][N] each */
   uint32_t* out;             /* device uint32[2][level-k+1][N] */
+  int* status;               /* host, optional: the job's own status (see below) */
 } mick_job;
 
 /* Workspace for mick_mul_relin_rescale_jobs: a job table plus one multiply
- * workspace per job.  0 for invalid jobs. */
+ * workspace per job.  A job with a status pointer whose (k, level) is out of
+ * range counts no workspace (it will be left out); any other such job makes
+ * the result 0. */
 size_t mick_jobs_workspace_bytes(const mick_params* prm, const mick_job* jobs, int n_jobs);
 
 /* n_jobs (1..65536) multiplies of one parameter set whose k and level may
@@ -210,7 +224,12 @@ size_t mick_jobs_workspace_bytes(const mick_params* prm, const mick_job* jobs, i
  * multiply is a single launch over a device job table (the tensor product
  * and the rescale are launched once per distinct k); each workgroup looks
  * its job up in the table.  jobs: host array; the table is copied into the
- * workspace (the copy reads `jobs` before the call returns). */
+ * workspace (the copy reads `jobs` before the call returns).
+ * Failure isolation: a job with a status pointer is validated on its own;
+ * if it is invalid its error code (MICK_E_ARG, MICK_E_LEVEL, MICK_E_KEY) is
+ * written there and it is left out while the other jobs run; a valid one
+ * gets MICK_OK.  An invalid job without a status pointer fails the whole
+ * call before anything is launched. */
 int mick_mul_relin_rescale_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs,
                                 void* ws, size_t ws_bytes, void* stream);
 
@@ -266,8 +285,16 @@ int mick_mul_tree(const mick_params* prm, const mick_keys* keys, const uint32_t*
  * device memory.  The queue owns one device workspace arena of `capacity`
  * bytes (from the registered allocator), allocated at creation.
  *
- *  - mick_queue_push appends jobs (all or none: any invalid job rejects the
- *    call) to a FIFO; it launches nothing.
+ *  - mick_queue_push appends jobs to a FIFO; it launches nothing.  A job
+ *    with a status pointer is accepted or refused on its own: refused, its
+ *    error code is written there (MICK_E_BUSY if its workspace alone exceeds
+ *    the queue's capacity); accepted, MICK_PENDING is written, then MICK_OK
+ *    when mick_queue_poll or mick_queue_drain sees it complete.  Jobs
+ *    without a status pointer are all or none: one invalid such job rejects
+ *    the call and nothing is appended.
+ *  - mick_queue_cancel removes the pending jobs with a given id (status
+ *    MICK_E_CANCELLED); MICK_E_BUSY if that id has already been launched,
+ *    MICK_E_ARG if no job with it is pending or running.
  *  - mick_queue_run admits pending jobs in FIFO order while the workspace of
  *    each fits a free block of the arena (first fit; it stops at the first
  *    job that does not fit, so admission stays in arrival order), groups the
@@ -299,6 +326,7 @@ typedef struct mick_qjob {
   int level;                 /* k..L of that set */
   const uint32_t* cts[12];   /* k device pointers, uint32[2][level][N] each */
   uint32_t* out;             /* device uint32[2][level-k+1][N] */
+  int* status;               /* host, optional: kept by the queue until the job completes */
 } mick_qjob;
 
 /* prms, keys: host arrays of n_sets (1..16) handles, keys[i] generated for
@@ -311,6 +339,7 @@ size_t mick_queue_job_bytes(const mick_queue* q, int set, int k, int level);
 int mick_queue_push(mick_queue* q, const mick_qjob* jobs, int n_jobs);
 int mick_queue_run(mick_queue* q, void* stream);
 int mick_queue_poll(mick_queue* q, uint64_t* done_ids, int max);
+int mick_queue_cancel(mick_queue* q, uint64_t id);
 int mick_queue_drain(mick_queue* q, void* stream);
 int mick_queue_info(const mick_queue* q, int* pending, int* running, size_t* bytes_in_use);
 void mick_queue_destroy(mick_queue* q);

@@ -445,6 +445,9 @@ const char* mick_strerror(int status) {
     case MICK_E_HIP: return "HIP runtime error";
     case MICK_E_RANGE: return "value out of range";
     case MICK_E_WS: return "workspace too small";
+    case MICK_E_BUSY: return "over the queue's budget, or already running";
+    case MICK_E_CANCELLED: return "cancelled";
+    case MICK_PENDING: return "pending";
     default: return "unknown status";
   }
 }
@@ -1118,20 +1121,21 @@ size_t job_ws_bytes(const mick_params* prm, int k, int level) {
 
 size_t table_bytes(int n_jobs) { return align_up((size_t)n_jobs * sizeof(JobDesc)); }
 
+int check_job(const mick_params* prm, const mick_keys* keys, const mick_job& jb) {
+  MICK_TRY(check_mul(prm, keys, jb.k, jb.level));
+  if (!jb.out) return set_error(MICK_E_ARG, "NULL output pointer");
+  for (int u = 0; u < jb.k; u++)
+    if (!jb.cts[u]) return set_error(MICK_E_ARG, "NULL ciphertext pointer");
+  return MICK_OK;
+}
+
 int check_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs) {
-  for (int i = 0; i < n_jobs; i++) {
-    const mick_job& jb = jobs[i];
-    MICK_TRY(check_mul(prm, keys, jb.k, jb.level));
-    if (!jb.out) return set_error(MICK_E_ARG, "NULL output pointer");
-    for (int u = 0; u < jb.k; u++)
-      if (!jb.cts[u]) return set_error(MICK_E_ARG, "NULL ciphertext pointer");
-  }
+  for (int i = 0; i < n_jobs; i++) MICK_TRY(check_job(prm, keys, jobs[i]));
   return MICK_OK;
 }
 
 int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs,
-              uint32_t* const* job_ws, JobDesc* table_dev, std::vector<JobDesc>& jt, hipStream_t s,
-              mick_plan** out) {
+              uint32_t* const* job_ws, JobDesc* table_dev, hipStream_t s, mick_plan** out) {
   std::unique_ptr<mick_plan> plan(new mick_plan());
   plan->prm = prm;
   plan->keys = keys;
@@ -1142,6 +1146,7 @@ int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* job
   std::vector<int> order(n_jobs);
   for (int i = 0; i < n_jobs; i++) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobs[a].k < jobs[b].k; });
+  std::vector<JobDesc>& jt = plan->host_table;
   jt.assign(n_jobs, JobDesc{});
   int total[kStages] = {0};
   for (int r = 0; r < n_jobs; r++) {
@@ -1172,7 +1177,8 @@ int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* job
     run.moddown_blocks = total[S_MODDOWN];
   }
   for (int st = 0; st < kStages; st++) plan->blocks[st] = total[st];
-  MICK_HIP(hipMemcpyAsync(table_dev, jt.data(), n_jobs * sizeof(JobDesc), hipMemcpyHostToDevice, s), "job table");
+  if (n_jobs > 0)
+    MICK_HIP(hipMemcpyAsync(table_dev, jt.data(), n_jobs * sizeof(JobDesc), hipMemcpyHostToDevice, s), "job table");
   *out = plan.release();
   return MICK_OK;
 }
@@ -1195,7 +1201,10 @@ size_t mick_jobs_workspace_bytes(const mick_params* prm, const mick_job* jobs, i
   size_t total = table_bytes(n_jobs);
   for (int i = 0; i < n_jobs; i++) {
     const int k = jobs[i].k, level = jobs[i].level;
-    if (k < 2 || k > kMaxK || level < k || level > prm->L) return 0;
+    if (k < 2 || k > kMaxK || level < k || level > prm->L) {
+      if (jobs[i].status) continue;  // left out of the batch
+      return 0;
+    }
     total += job_ws_bytes(prm, k, level);
   }
   return total;
@@ -1208,18 +1217,35 @@ int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job
   if (!prm || !keys || !jobs || !ws) return set_error(MICK_E_ARG, "NULL argument");
   if (keys->prm != prm) return set_error(MICK_E_ARG, "keys belong to other params");
   if (n_jobs < 1 || n_jobs > 65536) return set_error(MICK_E_ARG, "n_jobs must be in 1..65536");
-  MICK_TRY(check_jobs(prm, keys, jobs, n_jobs));
-  if (ws_bytes < mick_jobs_workspace_bytes(prm, jobs, n_jobs)) return set_error(MICK_E_WS, "workspace too small");
-  // table first, then the jobs' workspaces back to back
-  std::vector<uint32_t*> job_ws(n_jobs);
-  char* base = (char*)ws;
-  size_t off = align_up((size_t)n_jobs * sizeof(JobDesc));
+  // every job is checked before anything is written: a job with a status
+  // word that fails is left out, one without fails the call
+  std::vector<int> st(n_jobs, MICK_OK);
+  std::string first_error;
   for (int i = 0; i < n_jobs; i++) {
-    job_ws[i] = (uint32_t*)(base + off);
-    off += job_ws_bytes(prm, jobs[i].k, jobs[i].level);
+    st[i] = check_job(prm, keys, jobs[i]);
+    if (st[i] != MICK_OK && !jobs[i].status) return st[i];
+    if (st[i] != MICK_OK && first_error.empty()) first_error = mick_last_error();
   }
-  std::vector<JobDesc> host_table;
-  return plan_jobs(prm, keys, jobs, n_jobs, job_ws.data(), (JobDesc*)ws, host_table, (hipStream_t)stream, out);
+  std::vector<mick_job> valid;
+  valid.reserve(n_jobs);
+  for (int i = 0; i < n_jobs; i++)
+    if (st[i] == MICK_OK) valid.push_back(jobs[i]);
+  const int nv = (int)valid.size();
+  // table (sized for every job) first, then the valid jobs' workspaces
+  size_t off = table_bytes(n_jobs), need = off;
+  for (const mick_job& jb : valid) need += job_ws_bytes(prm, jb.k, jb.level);
+  if (ws_bytes < need) return set_error(MICK_E_WS, "workspace too small");
+  std::vector<uint32_t*> job_ws(nv);
+  char* base = (char*)ws;
+  for (int i = 0; i < nv; i++) {
+    job_ws[i] = (uint32_t*)(base + off);
+    off += job_ws_bytes(prm, valid[i].k, valid[i].level);
+  }
+  MICK_TRY(plan_jobs(prm, keys, valid.data(), nv, job_ws.data(), (JobDesc*)ws, (hipStream_t)stream, out));
+  for (int i = 0; i < n_jobs; i++)
+    if (jobs[i].status) *jobs[i].status = st[i];
+  if (!first_error.empty()) set_error(MICK_OK, first_error);  // detail of the first refused job
+  return MICK_OK;
 }
 
 int mick_plan_execute(const mick_plan* plan, void* stream) {
@@ -1228,6 +1254,7 @@ int mick_plan_execute(const mick_plan* plan, void* stream) {
   const mick_params* prm = plan->prm;
   const JobDesc* djt = plan->table;
   const int n = plan->n_jobs;
+  if (n == 0) return MICK_OK;  // every job was refused
   const GroupConsts G = group_consts(prm, plan->keys);
   for (size_t i = 0; i < plan->runs.size(); i++) {
     const auto& r = plan->runs[i];
@@ -1248,13 +1275,41 @@ int mick_plan_execute(const mick_plan* plan, void* stream) {
 
 void mick_plan_destroy(mick_plan* plan) { delete plan; }
 
+namespace {
+void destroy_plan_cb(void* plan) { mick_plan_destroy(static_cast<mick_plan*>(plan)); }
+}  // namespace
+
 int mick_mul_relin_rescale_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs,
                                 void* ws, size_t ws_bytes, void* stream) {
+  // this call frees its plan from a host function on the stream, which a
+  // graph would replay: capture takes mick_jobs_plan + mick_plan_execute
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  MICK_HIP(hipStreamIsCapturing((hipStream_t)stream, &cap), "capture status");
+  if (cap != hipStreamCaptureStatusNone)
+    return set_error(MICK_E_ARG, "stream is capturing: plan with mick_jobs_plan and capture mick_plan_execute");
   mick_plan* plan = nullptr;
   MICK_TRY(mick_jobs_plan(prm, keys, jobs, n_jobs, ws, ws_bytes, stream, &plan));
   const int st = mick_plan_execute(plan, stream);
-  mick_plan_destroy(plan);
+  // the plan holds the source of the table copy: free it once the stream
+  // has passed that copy (a host function queued behind the launches), or
+  // after a synchronisation if no host function can be queued
+  if (hipLaunchHostFunc((hipStream_t)stream, destroy_plan_cb, plan) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    mick_plan_destroy(plan);
+  }
   return st;
+}
+
+int mick_output_scale(const mick_params* prm, const double* scales_host, int k, int level, double* out_host) {
+  if (!prm || !scales_host || !out_host) return set_error(MICK_E_ARG, "NULL argument");
+  if (k < 2 || k > kMaxK) return set_error(MICK_E_ARG, "k must be in 2..12");
+  if (level < k || level > prm->L) return set_error(MICK_E_LEVEL, "level must be in k..L");
+  double sc = 1.0;
+  for (int u = 0; u < k; u++) sc *= scales_host[u];
+  for (int t = level - k + 1; t < level; t++) sc /= (double)prm->q[t];
+  *out_host = sc;
+  return MICK_OK;
 }
 
 int mick_ntt(const mick_params* prm, uint32_t* data_dev, int n_limbs, int first_prime, int inverse, void* stream) {

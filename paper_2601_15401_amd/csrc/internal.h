@@ -160,6 +160,9 @@ struct mick_plan {
     int j0, k, tensor_blocks, moddown_blocks;
   };
   std::vector<Run> runs;
+  // source of the asynchronous copy of the job table: lives as long as the
+  // plan, which the caller keeps until the copy has run
+  std::vector<mick::JobDesc> host_table;
 };
 
 struct mick_keys {
@@ -235,10 +238,11 @@ inline size_t evk_offset(const mick_params* prm, int t, int b, int l) {
 inline int digits_at(const mick_params* prm, int level) { return (level + prm->alpha - 1) / prm->alpha; }
 
 // Job tables (api.hip).  job_ws_bytes: one job's workspace (aligned);
-// table_bytes: a table of n_jobs entries (aligned).  check_jobs validates
-// shapes, keys and pointers.  plan_jobs writes the table of n_jobs jobs
-// (job i using the workspace job_ws[i]) to table_dev with an asynchronous
-// copy from jt, which the caller keeps alive until the copy has run.
+// table_bytes: a table of n_jobs entries (aligned).  check_job validates
+// one job's shape, keys and pointers; check_jobs every job.  plan_jobs
+// writes the table of n_jobs jobs (job i using the workspace job_ws[i]) to
+// table_dev with an asynchronous copy from the plan's own host table, so the
+// plan must outlive that copy.
 // One multiply's workspace in words (D, scaled d_t, ModUp outputs,
 // accumulators) and the relinearisation of the degree-k product D at the
 // start of `ws` followed by mu rescales (api.hip).
@@ -248,9 +252,9 @@ int relin_rescale_one(const mick_params* prm, const mick_keys* keys, int k, int 
 
 size_t job_ws_bytes(const mick_params* prm, int k, int level);
 size_t table_bytes(int n_jobs);
+int check_job(const mick_params* prm, const mick_keys* keys, const mick_job& job);
 int check_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs);
 int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* jobs, int n_jobs,
-              uint32_t* const* job_ws, JobDesc* table_dev, std::vector<JobDesc>& jt, hipStream_t s,
-              mick_plan** out);
+              uint32_t* const* job_ws, JobDesc* table_dev, hipStream_t s, mick_plan** out);
 
 }  // namespace mick

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "arena.h"
 #include "internal.h"
 
 using namespace mick;
@@ -18,53 +19,14 @@ namespace {
 constexpr int kMaxSets = 16;
 constexpr int kTableEntries = 65536;  // job-table entries of all running groups
 
-// First-fit allocator over [0, size) with coalescing of freed blocks.
-class Arena {
- public:
-  explicit Arena(size_t size) : size_(size) {
-    if (size) free_[0] = size;
-  }
-  // Offset of a block of `bytes` (a multiple of 256), or SIZE_MAX.
-  size_t take(size_t bytes) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < bytes) continue;
-      const size_t off = it->first, rest = it->second - bytes;
-      free_.erase(it);
-      if (rest) free_[off + bytes] = rest;
-      used_ += bytes;
-      return off;
-    }
-    return SIZE_MAX;
-  }
-  void give(size_t off, size_t bytes) {
-    used_ -= bytes;
-    auto nx = free_.lower_bound(off);
-    if (nx != free_.end() && off + bytes == nx->first) {
-      bytes += nx->second;
-      nx = free_.erase(nx);
-    }
-    if (nx != free_.begin()) {
-      auto pv = std::prev(nx);
-      if (pv->first + pv->second == off) {
-        pv->second += bytes;
-        return;
-      }
-    }
-    free_[off] = bytes;
-  }
-  size_t used() const { return used_; }
-
- private:
-  size_t size_, used_ = 0;
-  std::map<size_t, size_t> free_;  // offset -> length
-};
-
 struct Group {  // one launched plan
   hipEvent_t done = nullptr;
   std::vector<uint64_t> ids;
+  std::vector<int*> status;                       // the jobs' status words (NULL: none)
   std::vector<std::pair<size_t, size_t>> blocks;  // workspace arena (offset, bytes)
   std::pair<size_t, size_t> table;                // table area (offset, bytes)
-  std::vector<JobDesc> host_table;                // source of the table copy
+  mick_plan* plan = nullptr;                      // holds the source of the table copy
+  ~Group() { mick_plan_destroy(plan); }
 };
 
 }  // namespace
@@ -103,6 +65,8 @@ int reap(mick_queue* q, bool wait) {
     for (auto& b : (*it)->blocks) q->arena.give(b.first, b.second);
     q->tarena.give((*it)->table.first, (*it)->table.second);
     for (uint64_t id : (*it)->ids) q->done.push_back(id);
+    for (int* st : (*it)->status)
+      if (st) *st = MICK_OK;
     (void)hipEventDestroy((*it)->done);
     it = q->running.erase(it);
   }
@@ -151,22 +115,59 @@ size_t mick_queue_job_bytes(const mick_queue* q, int set, int k, int level) {
   return job_ws_bytes(prm, k, level);
 }
 
+namespace {
+
+int check_qjob(const mick_queue* q, const mick_qjob& jb) {
+  if (jb.set < 0 || jb.set >= (int)q->prms.size()) return set_error(MICK_E_ARG, "job names an unknown set");
+  mick_job one{};
+  one.k = jb.k;
+  one.level = jb.level;
+  memcpy(one.cts, jb.cts, sizeof(one.cts));
+  one.out = jb.out;
+  MICK_TRY(check_job(q->prms[jb.set], q->keys[jb.set], one));
+  if (qjob_bytes(q, jb) > q->capacity)
+    return set_error(MICK_E_BUSY, "a job's workspace exceeds the queue's memory budget");
+  return MICK_OK;
+}
+
+}  // namespace
+
 int mick_queue_push(mick_queue* q, const mick_qjob* jobs, int n_jobs) {
   if (!q || !jobs) return set_error(MICK_E_ARG, "NULL argument");
   if (n_jobs < 0) return set_error(MICK_E_ARG, "n_jobs < 0");
+  // all checks first: a refused job without a status word refuses the call
+  std::vector<int> st(n_jobs);
+  std::string first_error;
   for (int i = 0; i < n_jobs; i++) {
-    const mick_qjob& jb = jobs[i];
-    if (jb.set < 0 || jb.set >= (int)q->prms.size()) return set_error(MICK_E_ARG, "job names an unknown set");
-    mick_job one{};
-    one.k = jb.k;
-    one.level = jb.level;
-    memcpy(one.cts, jb.cts, sizeof(one.cts));
-    one.out = jb.out;
-    MICK_TRY(check_jobs(q->prms[jb.set], q->keys[jb.set], &one, 1));
-    if (qjob_bytes(q, jb) > q->capacity) return set_error(MICK_E_ARG, "a job's workspace exceeds the queue capacity");
+    st[i] = check_qjob(q, jobs[i]);
+    if (st[i] != MICK_OK && !jobs[i].status) return st[i];
+    if (st[i] != MICK_OK && first_error.empty()) first_error = mick_last_error();
   }
-  for (int i = 0; i < n_jobs; i++) q->pending.push_back(jobs[i]);
+  for (int i = 0; i < n_jobs; i++) {
+    if (jobs[i].status) *jobs[i].status = st[i] == MICK_OK ? MICK_PENDING : st[i];
+    if (st[i] == MICK_OK) q->pending.push_back(jobs[i]);
+  }
+  if (!first_error.empty()) set_error(MICK_OK, first_error);  // detail of the first refused job
   return MICK_OK;
+}
+
+int mick_queue_cancel(mick_queue* q, uint64_t id) {
+  if (!q) return set_error(MICK_E_ARG, "NULL queue");
+  int removed = 0;
+  for (auto it = q->pending.begin(); it != q->pending.end();) {
+    if (it->id != id) {
+      ++it;
+      continue;
+    }
+    if (it->status) *it->status = MICK_E_CANCELLED;
+    it = q->pending.erase(it);
+    removed++;
+  }
+  if (removed) return MICK_OK;
+  for (auto& g : q->running)
+    for (uint64_t r : g->ids)
+      if (r == id) return set_error(MICK_E_BUSY, "job already launched");
+  return set_error(MICK_E_ARG, "no pending or running job with this id");
 }
 
 int mick_queue_run(mick_queue* q, void* stream) {
@@ -221,14 +222,11 @@ int mick_queue_run(mick_queue* q, void* stream) {
       mj[i].out = js[i].out;
       ws[i] = (uint32_t*)(q->base + blocks[set][i].first);
       g->ids.push_back(js[i].id);
+      g->status.push_back(js[i].status);
     }
-    mick_plan* plan = nullptr;
-    int st = plan_jobs(q->prms[set], q->keys[set], mj.data(), n, ws.data(), (JobDesc*)(q->tables + toff[set]),
-                       g->host_table, s, &plan);
-    if (st == MICK_OK) {
-      st = mick_plan_execute(plan, stream);
-      mick_plan_destroy(plan);
-    }
+    int st = plan_jobs(q->prms[set], q->keys[set], mj.data(), n, ws.data(), (JobDesc*)(q->tables + toff[set]), s,
+                       &g->plan);
+    if (st == MICK_OK) st = mick_plan_execute(g->plan, stream);
     if (st == MICK_OK) st = hip_error(hipEventCreateWithFlags(&g->done, hipEventDisableTiming), "queue event");
     if (st == MICK_OK) st = hip_error(hipEventRecord(g->done, s), "queue event record");
     if (st != MICK_OK) {
@@ -238,6 +236,8 @@ int mick_queue_run(mick_queue* q, void* stream) {
       if (g->done) (void)hipEventDestroy(g->done);
       for (auto& b : g->blocks) q->arena.give(b.first, b.second);
       q->tarena.give(g->table.first, g->table.second);
+      for (int* js_st : g->status)
+        if (js_st) *js_st = st;
       status = st;
       continue;
     }

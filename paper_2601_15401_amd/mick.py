@@ -72,7 +72,9 @@ _SIGS = {
     "mick_queue_drain": (ctypes.c_int, [_vp, _vp]),
     "mick_queue_info": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "mick_queue_cancel": (ctypes.c_int, [_vp, ctypes.c_uint64]),
     "mick_queue_destroy": (None, [_vp]),
+    "mick_output_scale": (ctypes.c_int, [_vp, _c_dblp, ctypes.c_int, ctypes.c_int, _c_dblp]),
     "mick_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "mick_params_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mick_params_schedule": (ctypes.c_int, [_vp]),
@@ -89,13 +91,16 @@ _lib = None
 class Job(ctypes.Structure):
     """mick_job: one multiply of a heterogeneous batch."""
     _fields_ = [("k", ctypes.c_int), ("level", ctypes.c_int), ("cts", ctypes.c_void_p * 12),
-                ("out", ctypes.c_void_p)]
+                ("out", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
 class QJob(ctypes.Structure):
     """mick_qjob: one multiply pushed to a queue."""
     _fields_ = [("id", ctypes.c_uint64), ("set", ctypes.c_int), ("k", ctypes.c_int), ("level", ctypes.c_int),
-                ("cts", ctypes.c_void_p * 12), ("out", ctypes.c_void_p)]
+                ("cts", ctypes.c_void_p * 12), ("out", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+OK, E_ARG, E_LEVEL, E_KEY, E_NOMEM, E_HIP, E_RANGE, E_WS, E_BUSY, E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+PENDING = 1
 
 
 class MickError(RuntimeError):
@@ -333,20 +338,28 @@ def mul_relin_rescale_batch(prm: Params, keys: Keys, cts: torch.Tensor, level: i
     return out
 
 
-def make_jobs(prm: Params, specs):
+def make_jobs(prm: Params, specs, status=None):
     """specs: list of (cts, level, out) with cts a list of [2, level, N] tensors
-    and out a [2, level - k + 1, N] tensor or None.  Returns (ctypes array,
+    (None entries pass a NULL pointer) and out a [2, level - k + 1, N] tensor or
+    None.  status: optional ctypes int array, one status word per job (a job
+    whose shape is out of range then gets a one-word placeholder output, left
+    untouched by the library, which refuses the job).  Returns (ctypes array,
     outputs)."""
     arr = (Job * len(specs))()
     outs = []
     for i, (cts, level, out) in enumerate(specs):
         k = len(cts)
+        valid = 2 <= k <= 12 and k <= level <= prm.L
         if out is None:
-            out = _dev_empty(2, level - k + 1, prm.N)
+            if not valid and status is None:
+                raise ValueError("job %d: k=%d, level=%d out of range" % (i, k, level))
+            out = _dev_empty(2, level - k + 1, prm.N) if valid else _dev_empty(1)
         arr[i].k, arr[i].level = k, level
         for u, c in enumerate(cts):
-            arr[i].cts[u] = _ptr(c, 2 * level * prm.N, "ct").value
-        arr[i].out = _ptr(out, 2 * (level - k + 1) * prm.N, "out").value
+            arr[i].cts[u] = None if c is None else _ptr(c, 2 * level * prm.N if valid else 0, "ct").value
+        arr[i].out = _ptr(out, 2 * (level - k + 1) * prm.N if valid else 0, "out").value
+        if status is not None:
+            arr[i].status = ctypes.addressof(status) + i * ctypes.sizeof(ctypes.c_int)
         outs.append(out)
     return arr, outs
 
@@ -370,14 +383,25 @@ def jobs_workspace(prm: Params, arr) -> torch.Tensor:
     return _dev_empty((nbytes + 3) // 4)
 
 
-def mul_relin_rescale_jobs(prm: Params, keys: Keys, specs, ws=None):
-    """Heterogeneous batch: every job (k, level may differ) in one launch per stage."""
-    arr, outs = make_jobs(prm, specs)
+def mul_relin_rescale_jobs(prm: Params, keys: Keys, specs, ws=None, isolate: bool = False):
+    """Heterogeneous batch: every job (k, level may differ) in one launch per stage.
+    isolate: give every job a status word, so an invalid job is refused alone;
+    returns (outputs, statuses) then."""
+    st = (ctypes.c_int * len(specs))(*([E_HIP] * len(specs))) if isolate else None
+    arr, outs = make_jobs(prm, specs, st)
     if ws is None:
         ws = jobs_workspace(prm, arr)
     _check(load().mick_mul_relin_rescale_jobs(prm.handle, keys.handle, ctypes.cast(arr, _vp), len(arr), _ptr(ws),
                                               ws.numel() * 4, _stream()), "mick_mul_relin_rescale_jobs")
-    return outs
+    return (outs, list(st)) if isolate else outs
+
+
+def output_scale(prm: Params, scales, level: int) -> float:
+    """The scale of a k-input multiply's output at `level` (k = len(scales))."""
+    arr = (ctypes.c_double * len(scales))(*scales)
+    out = ctypes.c_double()
+    _check(load().mick_output_scale(prm.handle, arr, len(scales), level, ctypes.byref(out)), "mick_output_scale")
+    return out.value
 
 
 class Plan:
@@ -449,26 +473,44 @@ class Queue:
         h = _vp()
         _check(load().mick_queue_create(prms, keys, n, capacity, ctypes.byref(h)), "mick_queue_create")
         self._h = h
-        self._live = {}  # id -> tensors of the job
+        self._live = {}  # id -> tensors (and status words) of the job
+        self._status = {}  # id -> (status array, index)
 
     def job_bytes(self, set_index: int, k: int, level: int) -> int:
         return load().mick_queue_job_bytes(self._h, set_index, k, level)
 
-    def push(self, jobs):
+    def push(self, jobs, isolate: bool = False):
         """jobs: iterable of (id, set_index, cts, level, out) with cts k tensors
-        [2, level, N] and out a [2, level - k + 1, N] tensor."""
+        [2, level, N] and out a [2, level - k + 1, N] tensor.  isolate: every job
+        gets a status word (status(id)), so an invalid job is refused alone."""
         jobs = list(jobs)
         arr = (QJob * len(jobs))()
+        st_arr = (ctypes.c_int * len(jobs))(*([E_HIP] * len(jobs))) if isolate else None
         for i, (jid, st, cts, level, out) in enumerate(jobs):
             arr[i].id, arr[i].set, arr[i].k, arr[i].level = jid, st, len(cts), level
-            # an unknown set index is the library's to reject
+            # an unknown set index or shape is the library's to reject
             N = self.sets[st][0].N if 0 <= st < len(self.sets) else 0
+            ok_shape = 2 <= len(cts) <= 12 and len(cts) <= level and N > 0
             for u, c in enumerate(cts):
-                arr[i].cts[u] = _ptr(c, 2 * level * N, "ct").value
-            arr[i].out = _ptr(out, 2 * (level - len(cts) + 1) * N, "out").value
+                arr[i].cts[u] = None if c is None else _ptr(c, 2 * level * N if ok_shape else 0, "ct").value
+            arr[i].out = _ptr(out, 2 * (level - len(cts) + 1) * N if ok_shape else 0, "out").value
+            if isolate:
+                arr[i].status = ctypes.addressof(st_arr) + i * ctypes.sizeof(ctypes.c_int)
         _check(load().mick_queue_push(self._h, ctypes.cast(arr, _vp), len(jobs)), "mick_queue_push")
-        for jid, _st, cts, _lv, out in jobs:
-            self._live[jid] = (cts, out)
+        for i, (jid, _st, cts, _lv, out) in enumerate(jobs):
+            # the status words stay alive while the queue may write them
+            self._live.setdefault(jid, []).append((cts, out, st_arr))
+            if isolate:
+                self._status[jid] = (st_arr, i)
+
+    def status(self, jid):
+        """The status word of a job pushed with isolate=True."""
+        arr, i = self._status[jid]
+        return arr[i]
+
+    def cancel(self, jid):
+        """Removes the pending jobs with this id; MickError(E_BUSY) if it already runs."""
+        _check(load().mick_queue_cancel(self._h, jid), "mick_queue_cancel")
 
     def run(self) -> int:
         n = load().mick_queue_run(self._h, _stream())

@@ -120,3 +120,42 @@ def test_profile_site_selection_without_gpu():
     assert lib.mick_profile_select(b"tensor,") == -1  # an empty name is not a site
     assert lib.mick_profile_select(None) == 0
     assert lib.mick_profile_select(b"") == 0
+
+
+def test_job_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures against the C compiler's layout of
+    mick_job and mick_qjob (a layout mismatch would hand the library shifted
+    pointers)."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        import pytest
+        pytest.skip("gcc not available")
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mick.h"\n'
+                   'int main(void) {\n'
+                   ' printf("%zu %zu %zu %zu %zu\\n", sizeof(mick_job), offsetof(mick_job, level), '
+                   'offsetof(mick_job, cts), offsetof(mick_job, out), offsetof(mick_job, status));\n'
+                   ' printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(mick_qjob), offsetof(mick_qjob, set), '
+                   'offsetof(mick_qjob, level), offsetof(mick_qjob, cts), offsetof(mick_qjob, out), '
+                   'offsetof(mick_qjob, status));\n return 0; }\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], stdout=subprocess.PIPE, text=True, check=True).stdout.split("\n")
+    from paper_2601_15401_amd import mick
+    J, Q = mick.Job, mick.QJob
+    assert [int(x) for x in lines[0].split()] == [ctypes.sizeof(J), J.level.offset, J.cts.offset, J.out.offset,
+                                                  J.status.offset]
+    assert [int(x) for x in lines[1].split()] == [ctypes.sizeof(Q), Q.set.offset, Q.level.offset, Q.cts.offset,
+                                                  Q.out.offset, Q.status.offset]
+
+
+def test_status_words_and_cancel_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    lib.mick_strerror.restype = ctypes.c_char_p
+    assert lib.mick_strerror(-8) != b"unknown status" and lib.mick_strerror(-9) == b"cancelled"
+    assert lib.mick_strerror(1) == b"pending"
+    lib.mick_queue_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    assert lib.mick_queue_cancel(None, 5) == -1
+    lib.mick_output_scale.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int] * 2 + [ctypes.c_void_p]
+    assert lib.mick_output_scale(None, None, 3, 3, None) == -1
