@@ -193,6 +193,20 @@ int mick_rescale_multi(const mick_params* prm, const uint32_t* ct_in_dev, int le
 int mick_mul_relin_rescale(const mick_params* prm, const mick_keys* keys, const uint32_t* const* cts_host, int k,
                            int level, uint32_t* ct_out_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* The same multiply for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument and no allocation of any kind; the
+ * workspace is a static device array of 64 MiB (67108864 bytes) inside the
+ * library, one per device, held until the process ends.  MICK_E_WS when
+ * mick_workspace_bytes(prm, MICK_OP_MUL_RELIN_RESCALE, k, level) exceeds it
+ * (for instance N = 2^16 beyond small levels); nothing is launched then.
+ * Every call on one device shares that array: calls that overlap on a
+ * device (other streams, other threads) race, so the caller serialises
+ * them.  The multiply writes every workspace word it reads, so nothing has
+ * to be cleared between calls. */
+int mick_mul_relin_rescale_noalloc(const mick_params* prm, const mick_keys* keys, const uint32_t* const* cts_host,
+                                   int k, int level, uint32_t* ct_out_dev, void* stream);
+
 /* n_jobs (1..64) independent multiplies of the same (k, level) in one
  * sequence of launches, each kernel covering every job; the key inner
  * product reads each evaluation key element once for up to 8 jobs.

@@ -16,6 +16,14 @@
 
 using namespace mick;
 
+// Workspace of the allocation-free multiply (mick_mul_relin_rescale_noalloc):
+// one copy per device, held from the code object's load until the process
+// ends.  Host code never passes this name as an address: each device's copy
+// is reached through the pointer hipGetSymbolAddress returns for it, looked
+// up once per device and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint32_t scratch[kScratchBytes / 4];
+
 namespace mick {
 
 static thread_local std::string g_last_error;
@@ -454,6 +462,34 @@ const char* mick_strerror(int status) {
 
 const char* mick_last_error(void) { return g_last_error.c_str(); }
 
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch`, looked up once with that device current.
+int scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return set_error(MICK_E_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    MICK_HIP(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != device) MICK_HIP(hipSetDevice(device), "hipSetDevice");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    MICK_HIP(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return set_error(MICK_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return MICK_OK;
+}
+
+}  // namespace
+
 int mick_params_create(int log_n, int L, int K, int dnum, mick_params** out) {
   if (!out) return set_error(MICK_E_ARG, "NULL out");
   *out = nullptr;
@@ -480,6 +516,8 @@ int mick_params_create(int log_n, int L, int K, int dnum, mick_params** out) {
   p->split_a = split_a[log_n];
   p->split_b = log_n - p->split_a;
   MICK_HIP(hipGetDevice(&p->device), "hipGetDevice");
+  void* scratch_dev = nullptr;  // the allocation-free multiply's workspace on this device
+  MICK_TRY(scratch_address(p->device, &scratch_dev));
   int st = build_tables(p.get());
   if (st != MICK_OK) {
     mick_params_destroy(p.release());
@@ -949,6 +987,19 @@ int mick_mul_relin_rescale(const mick_params* prm, const mick_keys* keys, const 
   else
     MICK_TRY(launch_tensor(prm, in, 0, k, level, w + lay.D, 0, 1, s));
   return relin_rescale_ws(prm, keys, k, level, k - 1, w, lay.total, 1, ct_out_dev, 0, s, fuse);
+}
+
+int mick_mul_relin_rescale_noalloc(const mick_params* prm, const mick_keys* keys, const uint32_t* const* cts_host,
+                                   int k, int level, uint32_t* ct_out_dev, void* stream) {
+  MICK_TRY(check_mul(prm, keys, k, level));
+  const size_t need = mick_workspace_bytes(prm, MICK_OP_MUL_RELIN_RESCALE, k, level);
+  if (need > kScratchBytes)
+    return set_error(MICK_E_WS, "this multiply needs " + std::to_string(need) +
+                                    " bytes of workspace; the library's static workspace holds " +
+                                    std::to_string(kScratchBytes));
+  void* ws = nullptr;
+  MICK_TRY(scratch_address(prm->device, &ws));
+  return mick_mul_relin_rescale(prm, keys, cts_host, k, level, ct_out_dev, ws, kScratchBytes, stream);
 }
 
 size_t mick_batch_workspace_bytes(const mick_params* prm, int n_jobs, int k, int level) {

@@ -47,6 +47,8 @@ _SIGS = {
     "mick_rescale_multi": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp]),
     "mick_mul_relin_rescale": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _vp,
                                               ctypes.c_size_t, _vp]),
+    "mick_mul_relin_rescale_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int,
+                                                      _vp, _vp]),
     "mick_batch_workspace_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "mick_mul_relin_rescale_batch": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
                                                     _vp, ctypes.c_size_t, _vp]),
@@ -312,6 +314,18 @@ def mul_relin_rescale(prm: Params, keys: Keys, cts: Sequence[torch.Tensor], leve
     _check(load().mick_mul_relin_rescale(prm.handle, keys.handle, arr, k, level,
                                          _ptr(out, 2 * (level - k + 1) * prm.N, "out"), _ptr(ws),
                                          ws.numel() * 4, _stream()), "mick_mul_relin_rescale")
+    return out
+
+
+def mul_relin_rescale_noalloc(prm: Params, keys: Keys, cts: Sequence[torch.Tensor], level: int, out=None):
+    """The multiply on the library's static workspace (no allocation inside)."""
+    k = len(cts)
+    if out is None:
+        out = _dev_empty(2, level - k + 1, prm.N)
+    arr = (_vp * k)(*[_ptr(c, 2 * level * prm.N, "ct").value for c in cts])
+    _check(load().mick_mul_relin_rescale_noalloc(prm.handle, keys.handle, arr, k, level,
+                                                 _ptr(out, 2 * (level - k + 1) * prm.N, "out"), _stream()),
+           "mick_mul_relin_rescale_noalloc")
     return out
 
 
