@@ -30,8 +30,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one 32-bit integer VALU op per lane
-# per clock (gfx950 issues v_mul_lo/hi_u32 at full rate, measured).
+# per clock.  Measured on the device (mick_rates): v_mul_lo_u32 52,
+# v_mul_hi_u32 56, v_mad_u64_u32 50 lane-ops per CU per clock of the 64.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+MUL_LO_MEASURED_TOPS = 31.97
 
 WORKLOADS = {
     # name: (log_n, L, K, dnum, k, level, batch)
@@ -105,11 +107,46 @@ def site_work(site, N, k, level, K, alpha, jobs):
     return 0.0, 0.0
 
 
+def site_mults(site, N, k, level, K, alpha, jobs):
+    """32-bit integer multiplies of one launch at `site`, counted as the
+    whole-path work table does: a Shoup product by a constant is 3, a
+    Montgomery product or reduction 4, a 64-bit multiply-accumulate 2."""
+    E = level + K
+    B = -(-level // alpha)
+    mu = k - 1
+    new_limbs = (k - 1) * (B * E - level)
+    log_n = int(N).bit_length() - 1
+    stages_a = 8 if log_n >= 15 else 7
+    stages_b = log_n - stages_a
+    bf = N / 2 * 3.0  # Shoup products of one stage of one limb
+    if site == "modup_bconv_passA":
+        return jobs * new_limbs * (N * (2.0 * alpha + 4.0) + bf * stages_a)
+    if site == "passB_kip":
+        return jobs * ((new_limbs + 2 * E) * bf * stages_b + (k - 1) * B * E * N * 2 * 2.0 + 2 * E * N * 10.0)
+    if site.startswith("intt_d"):
+        return jobs * (k - 1) * level * bf * log_n
+    if site.startswith("intt_acc"):
+        return jobs * 2 * E * bf * log_n
+    if site.startswith("ntt_out"):
+        return jobs * 2 * (level - mu) * bf * log_n
+    if site == "tensor":
+        return jobs * level * N * (k * (k + 1) - 2) * 4.0
+    if site == "tensor_inttB":
+        return site_mults("tensor", N, k, level, K, alpha, jobs) + jobs * (k - 1) * level * bf * stages_b
+    if site == "moddown_rescale":
+        return jobs * 2 * (level - mu) * N * (2.0 * (K + mu) + 8.0)
+    return 0.0
+
+
 def roofline(prof, steps, N, k, level, K, alpha, jobs):
-    """Dominant kernel by total time.  Each pass of a two-pass transform is its
-    own kernel: it reads and writes every limb once and does half of the
-    transform's butterflies.  The bound is whichever of the HBM and VALU
-    fractions is larger."""
+    """Dominant kernel by total time (each pass of a two-pass transform is its
+    own kernel).  The fraction is the HBM roofline of the whole multiply:
+    the algorithmic bytes of the multiplies one launch serves (k inputs read,
+    the keys read once per batch, the output written; intermediates count
+    zero) over the dominant launch's duration, against 8 TB/s.  Beside it:
+    the kernel's own 32-bit multiplies (Shoup 3, Montgomery 4, 64-bit
+    multiply-add 2) against the int32 VALU peak, and, as a diagnostic, the
+    instruction model of site_work (bytes the kernel itself moves, VALU ops)."""
     table = []
     for site, (ms, cnt) in prof.items():
         base = site.split(".")[0]
@@ -124,15 +161,19 @@ def roofline(prof, steps, N, k, level, K, alpha, jobs):
         log("  %-18s %8.3f ms/step %4d launches  avg %8.1f us  %7.0f GB/s (%4.1f%% HBM)  %6.2f Tops (%4.1f%% ALU)"
             % (site, ms / steps, cnt, avg_s * 1e6, gbs, 100 * gbs / HBM_PEAK_GBS, tops, 100 * tops / ALU_PEAK_TOPS))
     ms, site, cnt, avg_s, gbs, tops, b, ops = table[0]
-    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, tops / ALU_PEAK_TOPS
-    if alu_frac > hbm_frac:
-        return {"kernel": site, "bound": "alu", "achieved": round(tops, 3), "peak": round(ALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(alu_frac, 4), "traffic": None,
-                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": b,
-                "hbm_frac_at_algorithmic_bytes": round(hbm_frac, 4)}
-    return {"kernel": site, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(hbm_frac, 4), "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
-            "algorithmic_bytes_per_launch": b, "alu_frac": round(alu_frac, 4)}
+    path_bytes = jobs * mult_bytes(N, k, level, K, alpha, jobs)
+    path_gbs = path_bytes / avg_s / 1e9
+    mults = site_mults(site.split(".")[0], N, k, level, K, alpha, jobs) / (2 if "." in site else 1)
+    mul_t = mults / avg_s / 1e12
+    return {"kernel": site, "bound": "hbm", "achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(path_gbs / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
+            "algorithmic_bytes_per_launch": int(path_bytes), "multiplies_per_launch": jobs,
+            "int32_mult": {"per_launch": int(mults), "achieved": round(mul_t, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                           "unit": "Tmul/s", "frac": round(mul_t / ALU_PEAK_TOPS, 4),
+                           "frac_of_measured_v_mul_lo_rate": round(mul_t / MUL_LO_MEASURED_TOPS, 4)},
+            "valu_model": {"kernel_bytes_per_launch": b, "kernel_bytes_frac": round(gbs / HBM_PEAK_GBS, 4),
+                           "valu_ops_per_launch": ops, "achieved_tops": round(tops, 3),
+                           "frac": round(tops / ALU_PEAK_TOPS, 4)}}
 
 
 def _code_tokens(text):
@@ -185,23 +226,68 @@ def mult_bytes(N, k, level, K, alpha, jobs):
     return inputs + keys + out
 
 
-def cpu_baseline(log_n, L, K, dnum, k, level):
-    """The oracle (exact numpy/Python-int path) on one multiply, one core."""
-    from oracle import keys as okeys, mult, params as oparams
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+_CPU_CASE = {}
+
+
+def _oracle_one(seed):
+    """One oracle multiply on seeded uniform inputs (pool worker; the
+    parameters and keys come from the parent by fork)."""
+    from oracle import mult
+    prm, ks, k, level = _CPU_CASE["case"]
+    rng = np.random.default_rng(seed)
+    cts = [np.stack([np.stack([rng.integers(0, q, prm.N, dtype=np.int64).astype(np.uint64) for q in prm.q[:level]])
+                     for _ in range(2)]) for _ in range(k)]
+    t0 = time.perf_counter()
+    mult.mul_relin_rescale(prm, ks, cts, level)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(log_n, L, K, dnum, k, level, pool=True):
+    """The oracle (exact numpy / Python-int path) timed on the host: one
+    multiply on one core, then one multiply per worker of a process pool
+    over the host's cores (at most 16) running concurrently."""
+    import multiprocessing as mp
+    from oracle import keys as okeys, params as oparams
     prm = oparams.make_params(log_n, L, K, dnum)
     log("cpu baseline: oracle keygen ...")
     ks = okeys.keygen(prm, 99, k)
-    rng = np.random.default_rng(99)
-    cts = [np.stack([np.stack([rng.integers(0, q, prm.N, dtype=np.int64).astype(np.uint64) for q in prm.q[:level]])
-                     for _ in range(2)]) for _ in range(k)]
-    log("cpu baseline: timing one multiply ...")
-    t0 = time.perf_counter()
-    mult.mul_relin_rescale(prm, ks, cts, level)
-    dt = time.perf_counter() - t0
+    _CPU_CASE["case"] = (prm, ks, k, level)
+    log("cpu baseline: timing one multiply on one core ...")
+    dt = _oracle_one(99)
     log("cpu baseline: %.1f s per multiply" % dt)
-    return {"value": round(1.0 / dt, 5), "unit": "ct-mults/s", "cores": 1, "kind": "oracle",
-            "sample": "one %d-input multiply at N=2^%d, level %d (tensor, relin, %d-level rescale), %.1f s; "
-                      "host %s" % (k, log_n, level, k - 1, dt, platform.processor() or platform.machine())}
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    workers = max(1, min(avail, 16))
+    model = cpu_model()
+    single = {"value": round(1.0 / dt, 5), "cores": 1, "seconds_per_mult": round(dt, 2)}
+    if not pool or workers < 2:
+        return {"value": single["value"], "unit": "ct-mults/s", "cores": 1, "kind": "oracle",
+                "sample": "one %d-input multiply at N=2^%d, level %d (tensor, relin, %d-level rescale), %.1f s on "
+                          "one core of %s" % (k, log_n, level, k - 1, dt, model), "cpu_model": model}
+    log("cpu baseline: %d multiplies on a pool of %d processes ..." % (workers, workers))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as p:
+        t0 = time.perf_counter()
+        per = p.map(_oracle_one, [1000 + i for i in range(workers)], chunksize=1)
+        wall = time.perf_counter() - t0
+    log("cpu baseline: pool %.1f s wall for %d multiplies" % (wall, workers))
+    return {"value": round(workers / wall, 5), "unit": "ct-mults/s", "cores": workers, "kind": "oracle",
+            "sample": "%d concurrent %d-input multiplies at N=2^%d, level %d (tensor, relin, %d-level rescale), "
+                      "one per process, %.1f s wall (%.1f s mean per multiply) on %s"
+                      % (workers, k, log_n, level, k - 1, wall, float(np.mean(per)), model),
+            "cpu_model": model, "single_core": single}
 
 
 def mixed_jobs(n_jobs, seed):
@@ -224,6 +310,24 @@ def job_bytes(N, k, level, K, alpha):
 
 
 def run_mixed(args, torch, mick):
+    """The mixed workload on its own: one JSON line."""
+    leg = mixed_leg(args, torch, mick, args.steps, args.warmup, args.plain_steps, with_queue=True,
+                    with_plain=not args.no_plain)
+    rec = {
+        "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
+        "value": leg["value"], "unit": "ct-mults/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": leg["ms_per_512"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "512 multiplies, N uniform over 2^13..2^16, k uniform 2..min(12,L), level "
+                               "uniform k..L, one graph of four job-table plans", "batch": 512,
+                   "parallelism": "none"},
+        **{k: v for k, v in leg.items() if k not in ("value", "ms_per_512")},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def mixed_leg(args, torch, mick, steps, warmup, plain_steps, with_queue=False, with_plain=True):
     """512 multiplies of mixed ring degree, k and level: the batched form runs
     one plan per ring degree (one launch per stage over a device job table),
     captured into one graph; the plain form launches each multiply alone."""
@@ -257,7 +361,7 @@ def run_mixed(args, torch, mick):
 
     log("warmup ...")
     mick.profile_enable(True)
-    for _ in range(args.warmup):
+    for _ in range(max(1, warmup)):
         step()
     torch.cuda.synchronize()
     mick.profile_collect()
@@ -270,13 +374,13 @@ def run_mixed(args, torch, mick):
             step()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record(stream)
-    for i in range(args.steps):
+    for i in range(steps):
         g.replay()
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
-    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     value = n_jobs / (step_ms.mean() / 1e3)
     log("batched (graph): %.3f ms per 512 multiplies, %.1f ct-mults/s" % (step_ms.mean(), value))
     # eager steps with the event profiler for the per-site breakdown
@@ -290,7 +394,7 @@ def run_mixed(args, torch, mick):
         log("  %-20s %8.3f ms/step %5d launches" % (site, ms / 2, cnt // 2))
 
     plain = None
-    if not args.no_plain:
+    if with_plain:
         wss = {ln: mick.workspace(prms[ln], mick.OP_MUL_RELIN_RESCALE, min(12, MIXED_PARAMS[ln][0]),
                                   MIXED_PARAMS[ln][0]) for ln in prms}
         outs = {ln: [torch.empty(2, lv - len(c) + 1, 1 << ln, dtype=torch.int32, device="cuda")
@@ -305,74 +409,98 @@ def run_mixed(args, torch, mick):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(args.plain_steps):
+        for _ in range(plain_steps):
             plain_step()
         e1.record(stream)
         torch.cuda.synchronize()
-        pms = e0.elapsed_time(e1) / args.plain_steps
+        pms = e0.elapsed_time(e1) / plain_steps
         plain = {"value": round(n_jobs / (pms / 1e3), 2), "unit": "ct-mults/s", "ms_per_512": round(pms, 3)}
         log("plain: %.3f ms per 512 multiplies, %.1f ct-mults/s" % (pms, n_jobs / (pms / 1e3)))
         for ln in specs:  # the two forms agree
             for o, b in zip(outs[ln], plans[ln].outs):
                 assert torch.equal(o, b)
-    # the same 512 jobs through the native work queue (host admission, one
-    # plan per ring degree per run, event completion), wall clock incl. host
-    order = sorted(prms)
-    qsets = [(prms[ln], keys[ln]) for ln in order]
-    qjobs, qi = [], 0
-    for ln in order:
-        for c, lv, _ in specs.get(ln, []):
-            qjobs.append((qi, order.index(ln), c, lv,
-                          torch.empty(2, lv - len(c) + 1, 1 << ln, dtype=torch.int32, device="cuda")))
-            qi += 1
-    qu = mick.Queue(qsets, capacity=1 << 36)
-    qu.push(qjobs)
-    qu.drain()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    queue = None
+    if with_queue:
+        # the same 512 jobs through the native work queue (host admission, one
+        # plan per ring degree per run, event completion), wall clock incl. host
+        order = sorted(prms)
+        qsets = [(prms[ln], keys[ln]) for ln in order]
+        qjobs, qi = [], 0
+        for ln in order:
+            for c, lv, _ in specs.get(ln, []):
+                qjobs.append((qi, order.index(ln), c, lv,
+                              torch.empty(2, lv - len(c) + 1, 1 << ln, dtype=torch.int32, device="cuda")))
+                qi += 1
+        qu = mick.Queue(qsets, capacity=1 << 36)
         qu.push(qjobs)
         qu.drain()
-    torch.cuda.synchronize()
-    q_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    log("queue: %.3f ms per 512 multiplies (wall), %.1f ct-mults/s" % (q_ms, n_jobs / (q_ms / 1e3)))
-    for ln in order:  # the queue's outputs equal the graph's
-        outs_q = [j[4] for j in qjobs if j[1] == order.index(ln)]
-        for o, b in zip(outs_q, plans[ln].outs):
-            assert torch.equal(o, b)
-    qu.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            qu.push(qjobs)
+            qu.drain()
+        torch.cuda.synchronize()
+        q_ms = (time.perf_counter() - t0) * 1e3 / steps
+        log("queue: %.3f ms per 512 multiplies (wall), %.1f ct-mults/s" % (q_ms, n_jobs / (q_ms / 1e3)))
+        for ln in order:  # the queue's outputs equal the graph's
+            outs_q = [j[4] for j in qjobs if j[1] == order.index(ln)]
+            for o, b in zip(outs_q, plans[ln].outs):
+                assert torch.equal(o, b)
+        qu.close()
+        queue = {"value": round(n_jobs / (q_ms / 1e3), 2), "unit": "ct-mults/s", "ms_per_512_wall": round(q_ms, 3)}
     total_bytes = sum(job_bytes(1 << ln, k, lv, MIXED_PARAMS[ln][1], prms[ln].alpha) for ln, k, lv in spec)
-    rec = {
-        "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
-        "value": round(value, 2), "unit": "ct-mults/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(float(step_ms.mean()), 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "512 multiplies, N uniform over 2^13..2^16, k uniform 2..min(12,L), level "
-                               "uniform k..L, one graph of four job-table plans", "batch": n_jobs,
-                   "parallelism": "none"},
-        "plain": plain,
+    leg = {
+        "value": round(value, 2), "unit": "ct-mults/s", "ms_per_512": round(float(step_ms.mean()), 4),
+        "steps": steps, "plain": plain,
         "batched_over_plain": round(value / plain["value"], 3) if plain else None,
-        "queue": {"value": round(n_jobs / (q_ms / 1e3), 2), "unit": "ct-mults/s", "ms_per_512_wall": round(q_ms, 3)},
         "schedules": schedules,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
-                       "p99": round(float(np.percentile(step_ms, 99)), 4), "of": "one batch of 512"},
+                       "p99": round(float(np.percentile(step_ms, 99)), 4), "of": "one graph replay of 512 multiplies"},
         "hbm_frac_whole_path": round(total_bytes / (step_ms.mean() / 1e3) / 1e9 / HBM_PEAK_GBS, 5),
         "algorithmic_bytes_per_mult": int(total_bytes / n_jobs),
+    }
+    if queue:
+        leg["queue"] = queue
+    del plans, g
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return leg
+
+
+def run_serve(args, torch, mick):
+    """The serving workload on its own: one JSON line."""
+    leg = serve_leg(args, torch, mick, 5000, (0.5, 0.8, 0.95))
+    top = leg["rates"][-1]
+    rec = {
+        "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
+        "value": top["ct_mults_per_s"], "unit": "ct-mults/s", "n_gpus": 1, "steps": 5000, "warmup": 64,
+        "ms_per_step": round(1e3 / top["ct_mults_per_s"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "serving: 5000 requests, open-loop Poisson at 0.95 x measured saturation, mixed N "
+                               "2^13..2^16 with 10%% heavy (N=2^16, k=12), HBM budget %d GB" % leg["hbm"]["budget_gb"],
+                   "batch": "continuous", "max_batch": args.serve_max_batch, "streams": args.serve_streams,
+                   "parallelism": "none"},
+        **{k: v for k, v in leg.items() if k != "hbm_budget"},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)
 
 
-def run_serve(args, torch, mick):
-    """Open-loop serving of 5000 requests (the mixed-workload mixture plus 10%
+def serve_leg(args, torch, mick, n_req, loads):
+    """Open-loop serving of n_req requests (the mixed-workload mixture plus 10%
     heavy N = 2^16, k = 12 requests) through the continuous-batching server:
     first all requests at once (saturation throughput), then Poisson
-    arrivals at 0.5 / 0.8 / 0.95 of that rate.  Latency is completion (a HIP
-    event after the request's plan) minus scheduled arrival."""
+    arrivals at the given fractions of that rate.  Latency is completion (a
+    HIP event after the request's plan) minus scheduled arrival."""
     from paper_2601_15401_amd import serve
-    n_req = 5000
     budget = 200 * 10 ** 9
     mix = serve.request_mix(n_req, 5, MIXED_PARAMS)
+    import gc
+    gc.collect()  # earlier legs' objects release their device memory first
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     free0, total = torch.cuda.mem_get_info()
     prms, keys, pools = {}, {}, {}
     for ln, (L, K, dnum) in MIXED_PARAMS.items():
@@ -400,7 +528,7 @@ def run_serve(args, torch, mick):
             out.append(serve.Request(i, ln, k, level, t, inputs=[pools[(ln, level)][u] for u in range(k)]))
         return out
 
-    check = set(range(0, n_req, 97))
+    check = set(range(0, n_req, 97 if n_req > 2000 else 29))
     ex = serve.GpuExecutor(mick, torch, prms, keys, n_streams=args.serve_streams, keep=lambda r: r.rid in check)
     srv = serve.Server(ex, budget, resident=resident, max_batch=args.serve_max_batch)
     log("warmup ...")
@@ -415,7 +543,7 @@ def run_serve(args, torch, mick):
     sat_rate = sat.summary()["ct_mults_per_s"]
     log("  %s host launch %.3f s" % (sat.summary(), ex.host_launch_s))
     results = []
-    for frac, seed in ((0.5, 50), (0.8, 51), (0.95, 52)):
+    for frac, seed in zip(loads, (50, 51, 52, 53, 54)):
         rate = frac * sat_rate
         log("open loop at %.2f x saturation = %.0f requests/s ..." % (frac, rate))
         ex.start()
@@ -438,7 +566,7 @@ def run_serve(args, torch, mick):
         assert torch.equal(o, r.output), "request %d differs from its plain multiply" % r.rid
     log("alone == in the mix for %d sampled requests" % len(kept))
     # plain: every request of a 500-request sample launched alone, back to back
-    sample = requests([0.0] * n_req)[:500]
+    sample = requests([0.0] * n_req)[:min(500, n_req)]
     wss = {ln: mick.workspace(prms[ln], mick.OP_MUL_RELIN_RESCALE, min(12, MIXED_PARAMS[ln][0]),
                               MIXED_PARAMS[ln][0]) for ln in prms}
     outs = [torch.empty(2, r.level - r.k + 1, 1 << r.log_n, dtype=torch.int32, device="cuda") for r in sample]
@@ -453,26 +581,24 @@ def run_serve(args, torch, mick):
     plain_rate = len(sample) / (e0.elapsed_time(e1) / 1e3)
     log("plain: %.1f ct-mults/s over the first %d requests" % (plain_rate, len(sample)))
     top = results[-1]
-    rec = {
-        "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
-        "value": top["ct_mults_per_s"], "unit": "ct-mults/s", "n_gpus": 1, "steps": n_req, "warmup": 64,
-        "ms_per_step": round(1e3 / top["ct_mults_per_s"], 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "serving: 5000 requests, open-loop Poisson at 0.95 x measured saturation, mixed N "
-                               "2^13..2^16 with 10%% heavy (N=2^16, k=12), HBM budget %d GB" % (budget // 10 ** 9),
-                   "batch": "continuous", "max_batch": args.serve_max_batch, "streams": args.serve_streams,
-                   "parallelism": "none"},
+    leg = {
+        "requests": n_req,
         "saturation_per_s": sat_rate,
         "rates": results,
-        "latency_ms": {"p50": top["p50_ms"], "p99": top["p99_ms"], "of": "one request, arrival to completion"},
-        "plain": {"value": round(plain_rate, 2), "unit": "ct-mults/s", "sample": "first 500 requests, each alone"},
+        "latency_ms": {"p50": top["p50_ms"], "p99": top["p99_ms"],
+                       "of": "one request, arrival to completion, at %.2f x saturation" % loads[-1]},
+        "plain": {"value": round(plain_rate, 2), "unit": "ct-mults/s",
+                  "sample": "first %d requests, each alone" % len(sample)},
         "served_over_plain": round(top["ct_mults_per_s"] / plain_rate, 3),
         "saturation_over_plain": round(sat_rate / plain_rate, 3),
+        "alone_equals_mix_checked": len(kept),
         "hbm": {"budget_gb": budget / 1e9, "resident_gb": round(resident / 1e9, 3),
                 "peak_gb": round(peak_hbm / 1e9, 3), "device_gb": round(total / 1e9, 1)},
-        "roofline": None, "cpu_baseline": None,
     }
-    print(json.dumps(rec), flush=True)
+    del pools, ex, srv
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return leg
 
 
 def relin_transforms(k, level, mu, K, alpha):
@@ -626,6 +752,10 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--serve-streams", type=int, default=4, help="serve5000: concurrent micro-batches")
     ap.add_argument("--serve-max-batch", type=int, default=32, help="serve5000: most requests per micro-batch")
+    ap.add_argument("--no-systems", action="store_true",
+                    help="default workload: skip the mixed-batch and serving legs")
+    ap.add_argument("--mixed-steps", type=int, default=5, help="default workload: graph replays of the mixed batch")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="default workload: requests of the serving leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized buffer once before timing (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -754,6 +884,18 @@ def main():
         log("unfused: %.3f ms per multiply, %.1f ct-mults/s" % (ums, 1e3 / ums))
 
     bytes_per_mult = mult_bytes(N, k, level, K, prm.alpha, jobs)
+    systems = {}
+    if args.workload == "n16_k8_b8" and not args.no_systems:
+        # the systems forms beside the headline batch: the mixed 512-multiply
+        # batch (graph of job-table plans against each multiply alone) and a
+        # shorter serving run with per-request latency
+        del cts, out, ws, lists
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log("mixed leg: 512 multiplies, %d graph replays ..." % args.mixed_steps)
+        systems["mixed512"] = mixed_leg(args, torch, mick, args.mixed_steps, 1, 1)
+        log("serving leg: %d requests ..." % args.serve_requests)
+        systems["serving"] = serve_leg(args, torch, mick, args.serve_requests, (0.5, 0.8, 0.95))
     cpu = None if args.no_cpu_baseline else cpu_baseline(log_n, L, K, dnum, k, level)
     rec = {
         "metric": "k-input ct-mults/s at N=2^16 (batched vs plain), % HBM peak; p50/p99 latency",
@@ -780,6 +922,7 @@ def main():
         "algorithmic_bytes_per_mult": int(bytes_per_mult),
         "roofline": rl,
         "cpu_baseline": cpu,
+        **systems,
     }
     print(json.dumps(rec), flush=True)
 
