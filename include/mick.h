@@ -259,6 +259,23 @@ int mick_jobs_plan(const mick_params* prm, const mick_keys* keys, const mick_job
 int mick_plan_execute(const mick_plan* plan, void* stream);
 void mick_plan_destroy(mick_plan* plan);
 
+/* ---------------------------------------------------------------- basis conversion
+ * The fast basis conversion of Sec. II, eq. (basis conversion), standalone,
+ * for n_polys polynomials of one digit: src_dev uint32[n_polys][na][N], the
+ * digit's na primes q_{b alpha} .. in the coefficient domain (canonical);
+ * dst_dev uint32[n_polys][level + K - na][N], the conversion into every
+ * other active q prime in ascending order, then p_0..p_{K-1}:
+ * out_e = sum_a [x_a qhat_a^-1]_{q_a} qhat_a mod m_e.  method 0: 64-bit
+ * multiply-add chains on the vector ALUs (the arithmetic of the fused ModUp
+ * kernel); method 1: int8 matrix cores on signed-byte splits with exact
+ * recombination.  Both give the same residues; digits of at most 8 primes.
+ * The conversion tables of a (level, digit) are built on first use (device
+ * memory from the registered allocator, kept until the parameters are
+ * destroyed).  Exposed to measure the two forms; the multiply itself runs
+ * the conversion inside its ModUp kernel. */
+int mick_bconv(const mick_params* prm, const uint32_t* src_dev, int n_polys, int level, int digit, uint32_t* dst_dev,
+               int method, void* stream);
+
 /* ---------------------------------------------------------------- tree multiply
  * Sec. V-C: the n inputs are partitioned into groups, recursively.  A node
  * multiplies the results of its children as polynomials in s (a group of g
@@ -359,21 +376,47 @@ int mick_queue_info(const mick_queue* q, int* pending, int* running, size_t* byt
 void mick_queue_destroy(mick_queue* q);
 
 /* ---------------------------------------------------------------- schedule
- * The transform splits log N into a first pass over 2^a rows and a second
- * over 2^(log N - a); the fused ModUp kernels exist for a in {7, 8} and
- * second passes of 6..8 stages, so N = 2^14 and 2^15 have two schedules
- * (N = 2^13: a = 7; N = 2^16: a = 8).  mick_autotune times the forward and
- * inverse transforms of L + K limbs under each schedule on the current
- * device and keeps the fastest; with a cache file it first looks up the
- * (device, N, L, K, dnum) entry and appends the result after timing (NULL:
- * the path in the environment variable MICK_AUTOTUNE_CACHE, else no cache).
- * Changing the schedule rebuilds the parameter tables (device work,
- * synchronous): call it before keys are generated or jobs are queued with
- * these parameters, never while work using them is in flight.
- * mick_params_schedule reports the first-pass log size a. */
+ * Three settings of a parameter set change how the multiply runs, never its
+ * result:
+ *  - the split of log N into a first transform pass over 2^a rows and a
+ *    second over 2^(log N - a) (a in {7, 8} where the passes fit: N = 2^14
+ *    and 2^15 have both, N = 2^13 only a = 7, N = 2^16 only a = 8);
+ *  - the tensor-product method (mick_params_set_tensor_method);
+ *  - ModUp targets per workgroup (1 or 2; 2 only for digits of 5 to 8
+ *    primes, where each source word loaded then feeds two conversions).
+ * mick_autotune times the fused multiply of a batch of two jobs at
+ * k = min(8, L) and level L on the current device (synthetic keys and
+ * inputs, allocated for the run and freed) under every combination, in
+ * three interleaved rounds, and keeps the combination with the smallest
+ * median time.  With a cache file it first looks up the (device, N, L, K,
+ * dnum) entry and appends the result after timing (NULL: the path in the
+ * environment variable MICK_AUTOTUNE_CACHE, else no cache).
+ * mick_autotune_report copies the last timing run's table (configs
+ * [max][3]: a, tensor method, ModUp targets; us: microseconds per multiply)
+ * and returns its length (0 after a cache hit).  Changing the split
+ * rebuilds the parameter tables (device work, synchronous): call these
+ * before jobs are queued with the parameters, never while work using them
+ * is in flight.  mick_params_schedule reports a. */
 int mick_autotune(mick_params* prm, const char* cache_path);
+int mick_autotune_report(const mick_params* prm, int max, int* configs, double* us);
 int mick_params_set_schedule(mick_params* prm, int first_pass_log);
 int mick_params_schedule(const mick_params* prm);
+int mick_params_set_modup_targets(mick_params* prm, int targets);
+int mick_params_modup_targets(const mick_params* prm);
+/* How the fused multiply forms d_0..d_k of eq. (d_u formula for n-ct mult)
+ * (every method gives the same residues):
+ *  0  one linear factor at a time, prod_{v<=u} (c0^v + c1^v Y), each new
+ *     coefficient an exact sum of two products reduced once;
+ *  1  a balanced binary tree of products of polynomials in Y, each node
+ *     coefficient an exact sum of its products reduced once;
+ *  2  the same tree with the reduced-multiplication forms at its nodes
+ *     (Karatsuba, Sec. II, for two linear factors and, on two levels, for
+ *     two cubics; the 3-parallel fast filter iterated as Sec. V-A suggests,
+ *     for two quadratics).
+ * The setting is read at launch; change it only while no work using the
+ * parameters is in flight.  mick_params_tensor_method reports it. */
+int mick_params_set_tensor_method(mick_params* prm, int method);
+int mick_params_tensor_method(const mick_params* prm);
 
 /* ---------------------------------------------------------------- allocator
  * Device memory of the library's own objects (parameter tables, keys,

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmick.so")
 RATES = os.path.join(PKG, "mick_rates")
-HIP_SOURCES = ["ntt.hip", "rns.hip", "api.hip", "queue.hip", "tree.hip"]
+HIP_SOURCES = ["ntt.hip", "tensor.hip", "rns.hip", "api.hip", "queue.hip", "tree.hip", "bconv.hip"]
 HOST_SOURCES = ["host_math.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are kept out of every kernel.

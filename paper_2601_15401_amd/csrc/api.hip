@@ -166,7 +166,7 @@ int build_tables(mick_params* prm) {
           int blk = b >> sl, rr = b & ((1 << sl) - 1);
           pos = (1 << s) + (rr << la) + blk;
         }
-        tw[2 * pos] = w;
+        tw[2 * pos] = 0u - w;  // stored negated: the forward butterfly forms -(Shoup product)
         tw[2 * pos + 1] = shoup_companion(w, m);
         itw[2 * pos] = wi;
         itw[2 * pos + 1] = shoup_companion(wi, m);
@@ -515,6 +515,8 @@ int mick_params_create(int log_n, int L, int K, int dnum, mick_params** out) {
   static const int split_a[17] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 7, 7, 8, 8};
   p->split_a = split_a[log_n];
   p->split_b = log_n - p->split_a;
+  p->tensor_method = kTensorChain;
+  p->modup_targets = 2;
   MICK_HIP(hipGetDevice(&p->device), "hipGetDevice");
   void* scratch_dev = nullptr;  // the allocation-free multiply's workspace on this device
   MICK_TRY(scratch_address(p->device, &scratch_dev));
@@ -536,6 +538,7 @@ static void free_tables(mick_params* prm) {
 }
 
 void mick_params_destroy(mick_params* prm) {
+  if (prm) bconv_release(prm);
   if (!prm) return;
   free_tables(prm);
   delete prm;
@@ -565,12 +568,65 @@ int mick_params_set_schedule(mick_params* prm, int first_pass_log) {
 
 int mick_params_schedule(const mick_params* prm) { return prm ? prm->split_a : set_error(MICK_E_ARG, "NULL params"); }
 
+int mick_params_set_tensor_method(mick_params* prm, int method) {
+  if (!prm) return set_error(MICK_E_ARG, "NULL params");
+  if (method < 0 || method >= kTensorMethods) return set_error(MICK_E_ARG, "tensor method must be 0, 1 or 2");
+  prm->tensor_method = method;
+  return MICK_OK;
+}
+
+int mick_params_tensor_method(const mick_params* prm) {
+  return prm ? prm->tensor_method : set_error(MICK_E_ARG, "NULL params");
+}
+
+int mick_params_set_modup_targets(mick_params* prm, int targets) {
+  if (!prm) return set_error(MICK_E_ARG, "NULL params");
+  if (targets != 1 && targets != 2) return set_error(MICK_E_ARG, "ModUp targets per workgroup must be 1 or 2");
+  if (targets == 2 && !modup_two_targets(prm->alpha))
+    return set_error(MICK_E_ARG, "two targets per workgroup need digits of 5 to 8 primes");
+  prm->modup_targets = targets;
+  return MICK_OK;
+}
+
+int mick_params_modup_targets(const mick_params* prm) {
+  if (!prm) return set_error(MICK_E_ARG, "NULL params");
+  return modup_pairs_on(prm) ? 2 : 1;
+}
+
+namespace {
+
+struct TuneConfig {
+  int a, tm, mt;
+};
+
+// Device time of `reps` fused multiplies of a batch of `jobs` with the
+// current settings (synthetic keys and inputs: the timing does not depend
+// on the values).
+int time_multiply(const mick_params* prm, const mick_keys* keys, int k, int level, int jobs, const uint32_t* cts,
+                  uint32_t* out, uint32_t* ws, size_t ws_bytes, int reps, hipEvent_t e0, hipEvent_t e1,
+                  double* us) {
+  MICK_TRY(mick_mul_relin_rescale_batch(prm, keys, cts, jobs, k, level, out, ws, ws_bytes, nullptr));  // warm-up
+  MICK_HIP(hipEventRecord(e0, nullptr), "event");
+  for (int r = 0; r < reps; r++)
+    MICK_TRY(mick_mul_relin_rescale_batch(prm, keys, cts, jobs, k, level, out, ws, ws_bytes, nullptr));
+  MICK_HIP(hipEventRecord(e1, nullptr), "event");
+  MICK_HIP(hipEventSynchronize(e1), "event");
+  float ms = 0;
+  MICK_HIP(hipEventElapsedTime(&ms, e0, e1), "event");
+  *us = 1e3 * ms / (reps * jobs);
+  return MICK_OK;
+}
+
+}  // namespace
+
 int mick_autotune(mick_params* prm, const char* cache_path) {
   if (!prm) return set_error(MICK_E_ARG, "NULL params");
-  std::vector<int> cand;
+  std::vector<TuneConfig> cand;
   for (int a : {7, 8})
-    if (schedule_ok(prm->log_n, a)) cand.push_back(a);
-  if (cand.size() == 1) return mick_params_set_schedule(prm, cand[0]);
+    if (schedule_ok(prm->log_n, a))
+      for (int tm = 0; tm < kTensorMethods; tm++)
+        for (int mt : {2, 1})
+          if (mt == 1 || modup_two_targets(prm->alpha)) cand.push_back({a, tm, mt});
   const char* path = cache_path ? cache_path : getenv("MICK_AUTOTUNE_CACHE");
   hipDeviceProp_t prop;
   MICK_HIP(hipGetDeviceProperties(&prop, prm->device), "device properties");
@@ -579,71 +635,109 @@ int mick_autotune(mick_params* prm, const char* cache_path) {
            prm->K, prm->dnum);
   for (char* c = key; *c; c++)
     if (*c == ':') *c = '_';  // keep the arch name one token
+  auto apply = [&](const TuneConfig& c) -> int {
+    if (prm->split_a != c.a) MICK_TRY(mick_params_set_schedule(prm, c.a));
+    MICK_TRY(mick_params_set_tensor_method(prm, c.tm));
+    return mick_params_set_modup_targets(prm, c.mt);
+  };
   if (path) {
     if (FILE* f = fopen(path, "r")) {
       char line[512];
       int found = 0;
+      TuneConfig best{};
       while (fgets(line, sizeof line, f)) {
         char arch[128];
-        int cus, ln, l, k, d, a;
+        int cus, ln, l, k, d, a, tm, mt;
         double us;
-        if (sscanf(line, "mick-schedule %127s %d %d %d %d %d %d %lf", arch, &cus, &ln, &l, &k, &d, &a, &us) != 8)
+        if (sscanf(line, "mick-tune %127s %d %d %d %d %d %d %d %d %lf", arch, &cus, &ln, &l, &k, &d, &a, &tm, &mt,
+                   &us) != 10)
           continue;
         char k2[256];
         snprintf(k2, sizeof k2, "%s %d %d %d %d %d", arch, cus, ln, l, k, d);
-        if (strcmp(k2, key) == 0 && schedule_ok(prm->log_n, a)) found = a;  // the last entry wins
+        for (const TuneConfig& c : cand)
+          if (strcmp(k2, key) == 0 && c.a == a && c.tm == tm && c.mt == mt) {
+            best = c;  // the last valid entry wins
+            found = 1;
+          }
       }
       fclose(f);
-      if (found) return mick_params_set_schedule(prm, found);
+      if (found) return apply(best);
     }
   }
-  // time forward + inverse transforms of all L + K limbs under each schedule
-  const int E = prm->L + prm->K;
-  const size_t words = (size_t)E * prm->N;
-  uint32_t* buf = nullptr;
-  MICK_TRY(dev_alloc(prm->alloc, &buf, words));
+  // time the fused multiply of a batch of two jobs at k = min(8, L), level L
+  // under every candidate, in interleaved rounds (the median of each is kept)
+  const int k = std::min(8, prm->L), level = prm->L, jobs = 2;
+  if (k < 2) return MICK_OK;  // a single prime: no multiply to time
+  const size_t N = prm->N, E = (size_t)prm->L + prm->K;
+  const size_t evk_words = (size_t)(k - 1) * prm->dnum * 2 * E * N;
+  const size_t in_words = (size_t)jobs * k * 2 * level * N;
+  const size_t out_words = (size_t)jobs * 2 * (level - k + 1) * N;
+  const size_t ws_bytes = mick_batch_workspace_bytes(prm, jobs, k, level);
+  uint32_t *evk = nullptr, *in = nullptr, *out = nullptr, *ws = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  int best = prm->split_a;
-  double best_us = 1e30;
+  mick_keys fake;  // synthetic key set: only the evaluation-key words are read
+  fake.prm = prm;
+  fake.k_max = k;
+  fake.seed = 0;
+  const TuneConfig start{prm->split_a, prm->tensor_method, prm->modup_targets};
+  std::vector<std::vector<double>> times(cand.size());
   int st = [&]() -> int {
-    MICK_HIP(hipMemset(buf, 0, words * 4), "autotune clear");
+    MICK_TRY(dev_alloc(prm->alloc, &evk, evk_words));
+    MICK_TRY(dev_alloc(prm->alloc, &in, in_words));
+    MICK_TRY(dev_alloc(prm->alloc, &out, out_words));
+    MICK_TRY(dev_alloc(prm->alloc, &ws, ws_bytes / 4 + 1));
+    // residues 0x11111111 < 2^29 are canonical for every prime here
+    MICK_HIP(hipMemset(evk, 0x11, evk_words * 4), "autotune fill");
+    MICK_HIP(hipMemset(in, 0x11, in_words * 4), "autotune fill");
     MICK_HIP(hipEventCreate(&e0), "event");
     MICK_HIP(hipEventCreate(&e1), "event");
-    const LimbMap mp = simple_map(prm, 0, E);
-    constexpr int kReps = 10;
-    for (int a : cand) {
-      MICK_TRY(mick_params_set_schedule(prm, a));
-      MICK_TRY(ntt_launch(prm, buf, buf, mp, E, 1, false, nullptr));  // warm-up
-      MICK_TRY(ntt_launch(prm, buf, buf, mp, E, 1, true, nullptr));
-      MICK_HIP(hipEventRecord(e0, nullptr), "event");
-      for (int r = 0; r < kReps; r++) {
-        MICK_TRY(ntt_launch(prm, buf, buf, mp, E, 1, false, nullptr));
-        MICK_TRY(ntt_launch(prm, buf, buf, mp, E, 1, true, nullptr));
+    fake.d_evk = evk;
+    constexpr int kRounds = 3, kReps = 4;
+    for (int round = 0; round < kRounds; round++)
+      for (size_t i = 0; i < cand.size(); i++) {
+        MICK_TRY(apply(cand[i]));
+        double us = 0;
+        MICK_TRY(time_multiply(prm, &fake, k, level, jobs, in, out, ws, ws_bytes, kReps, e0, e1, &us));
+        times[i].push_back(us);
       }
-      MICK_HIP(hipEventRecord(e1, nullptr), "event");
-      MICK_HIP(hipEventSynchronize(e1), "event");
-      float ms = 0;
-      MICK_HIP(hipEventElapsedTime(&ms, e0, e1), "event");
-      const double us = 1e3 * ms / kReps;
-      if (us < best_us) {
-        best_us = us;
-        best = a;
-      }
-    }
     return MICK_OK;
   }();
+  fake.d_evk = nullptr;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  dev_free(prm->alloc, buf);
-  MICK_TRY(st);
-  MICK_TRY(mick_params_set_schedule(prm, best));
+  (void)hipDeviceSynchronize();
+  for (uint32_t* b : {evk, in, out, ws}) dev_free(prm->alloc, b);
+  if (st != MICK_OK) {
+    (void)apply(start);
+    return st;
+  }
+  size_t best = 0;
+  prm->tune_table.clear();
+  std::vector<double> med(cand.size());
+  for (size_t i = 0; i < cand.size(); i++) {
+    std::sort(times[i].begin(), times[i].end());
+    med[i] = times[i][times[i].size() / 2];
+    prm->tune_table.push_back({(double)cand[i].a, (double)cand[i].tm, (double)cand[i].mt, med[i]});
+    if (med[i] < med[best]) best = i;
+  }
+  MICK_TRY(apply(cand[best]));
   if (path) {
     if (FILE* f = fopen(path, "a")) {
-      fprintf(f, "mick-schedule %s %d %.2f\n", key, best, best_us);
+      fprintf(f, "mick-tune %s %d %d %d %.2f\n", key, cand[best].a, cand[best].tm, cand[best].mt, med[best]);
       fclose(f);
     }
   }
   return MICK_OK;
+}
+
+int mick_autotune_report(const mick_params* prm, int max, int* configs, double* us) {
+  if (!prm || (max > 0 && (!configs || !us))) return set_error(MICK_E_ARG, "NULL argument");
+  const int n = std::min(max, (int)prm->tune_table.size());
+  for (int i = 0; i < n; i++) {
+    for (int j = 0; j < 3; j++) configs[3 * i + j] = (int)prm->tune_table[i][j];
+    us[i] = prm->tune_table[i][3];
+  }
+  return (int)prm->tune_table.size();
 }
 
 int mick_params_moduli(const mick_params* prm, uint32_t* q_host, uint32_t* p_host) {
@@ -1099,7 +1193,7 @@ void job_blocks(const mick_params* prm, int k, int level, int (&nb)[kStages]) {
   nb[S_TENSOR] = pad8((prm->N >> tib_tile_log(k)) * level);  // k_tensor_ib_jt
   nb[S_INTT_D] = pad8(tiles * (k - 1) * level);
   nb[S_MODUP] = pad8((k - 1) * B * (1 << (prm->log_n - kModupTileLog))) *
-                (modup_two_targets(prm->alpha) ? modup_pairs(level, E) : E);
+                (modup_pairs_on(prm) ? modup_pairs(level, E) : E);
   nb[S_KIP] = pad8(E * (1 << (prm->log_n - kKipTileLog)));
   nb[S_INTT_ACC] = pad8(tiles * 2 * E);
   nb[S_MODDOWN] = pad8(2 * (prm->N / 256));

@@ -146,6 +146,11 @@ struct mick_params {
   // host copies of psi per prime
   std::vector<uint32_t> psi;
   int split_a, split_b;  // log2 rows of the two NTT passes
+  int tensor_method;     // TensorMethod of the fused tensor kernels
+  int modup_targets;     // ModUp targets per workgroup for digits of 5..8 primes (1 or 2)
+  // the last mick_autotune's timings: (first-pass log, tensor method, ModUp
+  // targets, microseconds per multiply)
+  std::vector<std::vector<double>> tune_table;
 };
 
 // A heterogeneous batch ready to run: the job table lives in the caller's
@@ -229,6 +234,8 @@ int ntt_launch(const mick_params* prm, const uint32_t* src, uint32_t* dst, const
 int intt_pass_a_launch(const mick_params* prm, uint32_t* buf, const LimbMap& map, int n_limbs, int n_jobs,
                        hipStream_t s, int site);
 LimbMap simple_map(const mick_params* prm, int first_prime, int n_limbs);
+// Frees the standalone basis-conversion tables built for `prm` (bconv.hip).
+void bconv_release(const mick_params* prm);
 
 inline size_t evk_offset(const mick_params* prm, int t, int b, int l) {
   size_t limbs = (size_t)(prm->L + prm->K);

@@ -70,6 +70,28 @@ __device__ __forceinline__ void mac96(uint64_t& lo, uint32_t& hi, uint32_t a, ui
       : "v"(a), "v"(b));
 }
 
+// lo32(a b + c d): two chained 32 x 32 + 64-bit multiply-adds, the first
+// product's 64-bit result feeding the second as its addend; only the low
+// word is kept.  The low word of a 64-bit sum depends only on the low words
+// of its terms, so this is (a b + c d) mod 2^32 exactly.  One instruction
+// per product, where a 32-bit multiply and a separate add would take two
+// for the second.  d is uniform across the wave (a modulus or its negation).
+__device__ __forceinline__ uint32_t mad2_lo(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  uint64_t p, cy;  // cy: carry-out lane mask, unused
+  asm("v_mad_u64_u32 %0, %1, %2, %3, 0\n\t"
+      "v_mad_u64_u32 %0, %1, %4, %5, %0"
+      : "=&v"(p), "=&s"(cy)
+      : "v"(a), "v"(b), "v"(c), "s"(d));
+  return (uint32_t)p;
+}
+
+// Shoup product in [0, 2m) with negm = 2^32 - m: y w + floor(y w' / 2^32)
+// (2^32 - m) mod 2^32 = y w - floor(y w' / 2^32) m, the value of shoup_lazy
+// in three instructions.
+__device__ __forceinline__ uint32_t shoup_lazy_neg(uint32_t y, uint32_t w, uint32_t wsh, uint32_t negm) {
+  return mad2_lo(y, w, __umulhi(y, wsh), negm);
+}
+
 // Per-modulus constants for reducing a full 64-bit value.
 struct Red64 {
   uint32_t m;

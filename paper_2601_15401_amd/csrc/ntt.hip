@@ -1,34 +1,9 @@
 // Negacyclic NTT / INTT for N = 2^13 .. 2^16 on gfx950, and the two fused
 // kernels of the ModUp path that are built on the same transform passes.
 //
-// The transform is the merged-twiddle Cooley-Tukey factorisation of
-// NTT(a)[k] = a(psi^(2 brv(k) + 1)): stage s (s = 0 .. log N - 1) splits the
-// vector into 2^s blocks and butterflies element pairs half a block apart
-// with twiddle psi^brv(2^s + b) for block b.  The inverse runs the stages in
-// reverse with Gentleman-Sande butterflies and psi^-brv(.), and the factor
-// N^-1 is merged into its last stage.
+// The transform passes are built from ntt_core.h; the fused tensor-product
+// kernel is in tensor.hip.
 //
-// Two passes cover the log N stages: pass A the first LA stages (element
-// pairs that differ in the high LA index bits), pass B the last LB stages.
-// A workgroup owns a tile of one limb (8192 elements; 1024 in the key-product
-// kernel): 2^LOGR butterfly rows by tile / 2^LOGR independent columns (pass
-// A: columns are consecutive low indices; pass B: columns are consecutive
-// 2^LB-element blocks).  A pass is
-// two radix-8/16 rounds in registers: the "strided" round (the pass's first
-// RB0 stages, row stride 2^(LOGR-RB0)) and the "consecutive" round (the last
-// RB1 stages, 2^RB1 neighbouring rows).  The first round of a pass loads
-// straight from global memory into registers, the tile crosses LDS once
-// between the rounds, and the second round stores straight to global
-// memory.  Lane-to-item maps are chosen per pass and round so that global
-// accesses are coalesced (pass B's consecutive round moves 16 neighbouring
-// words per lane with 128-bit accesses); pass-B twiddles are stored
-// transposed per stage so that lanes holding neighbouring blocks read
-// neighbouring twiddles.
-//
-// Arithmetic: Shoup products by precomputed twiddles.  Limbs whose prime is
-// below 2^30 use Harvey's lazy butterflies (values kept below 4q); the
-// 31-bit special primes keep values below 2q with one more conditional
-// subtraction per butterfly.  The last pass stores canonical residues.
 //
 // ModUp fusion (Sec. II ModUp, Sec. III combined key products):
 //  * k_modup_a: the fast basis conversion of eq. (basis conversion) computed
@@ -44,297 +19,11 @@
 //    already in the inverse transform's first-round layout, so the first
 //    pass (pass B) of the accumulators' INTT (Sec. IV relocated ModDown)
 //    runs in the same kernel and only its output is written.
-#include "internal.h"
-#include "rns.h"
+#include "ntt_core.h"
 
 namespace mick {
 
 namespace {
-
-constexpr int kThreads = 256;
-constexpr int kTileLog = 13;
-
-// TL: log2 of the tile's element count (8192 for the transform passes).
-template <int LOGR, int TL = kTileLog>
-struct Geo {
-  static constexpr int LOGC = TL - LOGR;
-  static constexpr int COLS = 1 << LOGC;
-  static constexpr int RB0 = (LOGR == 6) ? 3 : 4;
-  static constexpr int RB1 = LOGR - RB0;
-  // LDS row pitch.  Pass B's strided round gives each column 2^(LOGR-RB0)
-  // consecutive lanes (rows lo, lo + 2^(LOGR-RB0), ...), so a 32-lane half
-  // touches 32 >> (LOGR-RB0) columns; a pitch of COLS + that count puts
-  // their lanes on distinct banks.  Every other round has 32 consecutive
-  // columns of one row per half, conflict-free at any pitch.
-  static constexpr int PAD = COLS + (32 >> (LOGR - RB0));
-  static constexpr int LDS_WORDS = (1 << LOGR) * PAD;
-};
-
-// Item layout of one round.  An item is one column c and 2^RB rows
-// rbase + j 2^NLO_LOG, j < 2^RB.
-template <int LOGR, bool PASSB, bool STRIDED, int NT = kThreads, int TL = kTileLog>
-struct Rnd {
-  using G = Geo<LOGR, TL>;
-  static constexpr int RB = STRIDED ? G::RB0 : G::RB1;
-  static constexpr int E = 1 << RB;
-  static constexpr int SL0 = STRIDED ? 0 : G::RB0;  // first local stage of the round
-  static constexpr int NLO_LOG = STRIDED ? LOGR - G::RB0 : 0;
-  static constexpr int ITEMS = (1 << TL) >> RB;
-  static constexpr int NI = ITEMS / NT;  // items per thread
-  // pass B's strided round walks the rows of a column with consecutive lanes
-  static constexpr bool LO_FAST = PASSB && STRIDED;
-  // pass B's consecutive round moves 2^RB neighbouring words per lane
-  static constexpr bool VEC = PASSB && !STRIDED;
-
-  __device__ static void decode(int it, int& c, int& rbase, int& hi) {
-    int lo;
-    if constexpr (LO_FAST) {
-      lo = it & ((1 << NLO_LOG) - 1);
-      c = it >> NLO_LOG;
-      hi = 0;
-    } else {
-      c = it & (G::COLS - 1);
-      const int hl = it >> G::LOGC;
-      lo = STRIDED ? hl : 0;
-      hi = STRIDED ? 0 : hl;
-    }
-    rbase = (hi << (LOGR - SL0)) + lo;
-  }
-  __device__ static int row(int rbase, int j) { return rbase + (j << NLO_LOG); }
-  __device__ static uint32_t gidx(int H, int col, int r) {  // < N <= 2^16
-    return PASSB ? ((uint32_t)col << LOGR) + r : ((uint32_t)r << H) + col;
-  }
-};
-
-// Forward (Cooley-Tukey) butterfly.
-template <bool LAZY>
-__device__ __forceinline__ void ct(uint32_t& x, uint32_t& y, uint2 w, uint32_t q) {
-  if constexpr (LAZY) {  // x, y < 4q -> outputs < 4q
-    uint32_t a = min(x, x - 2 * q);
-    uint32_t t = shoup_lazy(y, w.x, w.y, q);
-    x = a + t;
-    y = a - t + 2 * q;
-  } else {  // x, y < 2q -> outputs < 2q
-    uint32_t a = red1(x, q);
-    uint32_t t = red1(shoup_lazy(y, w.x, w.y, q), q);
-    x = a + t;
-    y = a - t + q;
-  }
-}
-
-// Inverse (Gentleman-Sande) butterfly, values < 2q throughout.
-template <bool LAZY>
-__device__ __forceinline__ void gs(uint32_t& x, uint32_t& y, uint2 w, uint32_t q) {
-  if constexpr (LAZY) {
-    uint32_t u = x + y;
-    uint32_t v = x - y + 2 * q;
-    x = min(u, u - 2 * q);
-    y = shoup_lazy(v, w.x, w.y, q);
-  } else {
-    uint32_t a = red1(x, q), b = red1(y, q);
-    x = a + b;
-    y = shoup_lazy(a - b + q, w.x, w.y, q);
-  }
-}
-
-// The last inverse stage with N^-1 (times a per-limb factor) merged into both
-// outputs: nf = (f, f', w1 f, (w1 f)').
-template <bool LAZY>
-__device__ __forceinline__ void gs_last(uint32_t& x, uint32_t& y, const uint4& nf, uint32_t q) {
-  if constexpr (LAZY) {
-    uint32_t u = x + y, v = x - y + 2 * q;
-    x = shoup_lazy(u, nf.x, nf.y, q);
-    y = shoup_lazy(v, nf.z, nf.w, q);
-  } else {
-    uint32_t a = red1(x, q), b = red1(y, q);
-    x = shoup_lazy(a + b, nf.x, nf.y, q);
-    y = shoup_lazy(a - b + q, nf.z, nf.w, q);
-  }
-}
-
-template <bool FWD, bool LAZY>
-__device__ __forceinline__ uint32_t canonical(uint32_t v, uint32_t q) {
-  if constexpr (FWD && LAZY) v = min(v, v - 2 * q);
-  return red1(v, q);
-}
-
-// Butterflies of one item: fetches the round's twiddles (stage u of the
-// round uses 2^u of them; TW(s, rr) returns the twiddle of global stage s,
-// local block rr), then runs the RB stages in order (forward) or reverse
-// order (inverse).  HAS_STAGE0: the round contains global stage 0 of an
-// inverse transform, which takes nfix instead of a twiddle.
-template <int RB, bool FWD, bool LAZY, bool HAS_STAGE0, typename TW>
-__device__ __forceinline__ void item_bfly_t(uint32_t (&x)[1 << RB], const TW& twf, int s_first, int hi, uint32_t q,
-                                            const uint4& nfix) {
-  constexpr int E = 1 << RB;
-  uint2 w[E];
-#pragma unroll
-  for (int u = 0; u < RB; u++) {
-    if (HAS_STAGE0 && u == 0) continue;
-#pragma unroll
-    for (int g = 0; g < (1 << u); g++) w[(1 << u) + g] = twf(s_first + u, u, (hi << u) + g);
-  }
-  if constexpr (FWD) {
-#pragma unroll
-    for (int u = 0; u < RB; u++) {
-      const int half = 1 << (RB - 1 - u);
-#pragma unroll
-      for (int j = 0; j < E; j++) {
-        if (j & half) continue;
-        ct<LAZY>(x[j], x[j + half], w[(1 << u) + (j >> (RB - u))], q);
-      }
-    }
-  } else {
-#pragma unroll
-    for (int u = RB - 1; u >= 0; u--) {
-      const int half = 1 << (RB - 1 - u);
-#pragma unroll
-      for (int j = 0; j < E; j++) {
-        if (j & half) continue;
-        if (HAS_STAGE0 && u == 0)
-          gs_last<LAZY>(x[j], x[j + half], nfix, q);
-        else
-          gs<LAZY>(x[j], x[j + half], w[(1 << u) + (j >> (RB - u))], q);
-      }
-    }
-  }
-}
-
-// Twiddles read from the per-prime table in global memory.
-struct TwGlobal {
-  const uint2* tw;
-  int s0, blk;
-  __device__ uint2 operator()(int s, int, int rr) const { return tw[(1 << s) + (rr << s0) + blk]; }
-};
-
-// Pass A's twiddles do not depend on the column: a tile uses tw[1 .. 2^LOGR)
-// of its prime, staged in LDS once per block.
-struct TwPassA {
-  const uint2* t;
-  __device__ uint2 operator()(int s, int, int rr) const { return t[(1 << s) + rr]; }
-};
-
-template <int LOGR, int NT = kThreads>
-__device__ __forceinline__ void stage_tw_pass_a(uint2* ltwa, const uint2* tw) {
-  for (int i = threadIdx.x; i < (1 << LOGR); i += NT) ltwa[i] = tw[i];
-}
-
-// The tile's pass-B twiddles staged in LDS: stage s0 + sl, block rr < 2^sl,
-// column c < COLS at COLS (2^sl - 1) + rr COLS + c.
-template <int COLS>
-struct TwLds {
-  const uint2* t;
-  int s0, c;
-  __device__ uint2 operator()(int s, int, int rr) const {
-    const int sl = s - s0;
-    return t[COLS * ((1 << sl) - 1) + rr * COLS + c];
-  }
-};
-
-// Stages the pass-B twiddles of the tile's first NSL stages (sl < NSL) in
-// the TwLds layout; every load is issued before the first LDS store.
-template <int COLS, int NSL, int NT>
-__device__ __forceinline__ void stage_tw_pass_b(uint2* ltw, const uint2* tw, int s0, int col0) {
-  constexpr int LOGC = __builtin_ctz(COLS);
-  constexpr int NTW = COLS * ((1 << NSL) - 1);
-  constexpr int IT = (NTW + NT - 1) / NT;
-  uint2 t[IT];
-#pragma unroll
-  for (int it = 0; it < IT; it++) {
-    const int i = it * NT + threadIdx.x;
-    if (i < NTW) {
-      const int c = i & (COLS - 1);
-      const int k = i >> LOGC;  // (2^sl - 1) + rr
-      const int sl = 31 - __clz(k + 1);
-      const int rr = k + 1 - (1 << sl);
-      t[it] = tw[(1 << (s0 + sl)) + (rr << s0) + col0 + c];
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < IT; it++) {
-    const int i = it * NT + threadIdx.x;
-    if (i < NTW) ltw[i] = t[it];
-  }
-}
-
-// LDS twiddle words of a transform pass: the forward pass A stages pass A's
-// twiddles; the inverse pass B at LOGR = 8 stages its strided round's
-// per-column twiddles (3.75 KB, which keeps four workgroups per CU).
-template <int LOGR, bool FWD, bool PASSB>
-constexpr int pass_tw_words() {
-  return FWD && !PASSB ? 1 << LOGR : (!FWD && PASSB && LOGR == 8 ? Geo<LOGR>::COLS * ((1 << Geo<LOGR>::RB0) - 1) : 1);
-}
-
-template <int RB, bool FWD, bool LAZY, bool HAS_STAGE0>
-__device__ __forceinline__ void item_bfly(uint32_t (&x)[1 << RB], const uint2* tw, int s_first, int s0, int hi,
-                                          int blk, uint32_t q, const uint4& nfix) {
-  item_bfly_t<RB, FWD, LAZY, HAS_STAGE0>(x, TwGlobal{tw, s0, blk}, s_first, hi, q, nfix);
-}
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// Global accesses of one item.  STREAM marks data touched once per pass
-// (nontemporal: it should not displace the twiddles other tiles reuse).
-template <typename RD, bool STREAM = false>
-__device__ __forceinline__ void load_global(uint32_t (&x)[RD::E], const uint32_t* g, int H, int col, int rbase) {
-  if constexpr (RD::VEC) {
-#pragma unroll
-    for (int j = 0; j < RD::E; j += 4) {
-      const u32x4* p = reinterpret_cast<const u32x4*>(g + RD::gidx(H, col, rbase + j));
-      const u32x4 v = STREAM ? __builtin_nontemporal_load(p) : *p;
-      x[j] = v.x;
-      x[j + 1] = v.y;
-      x[j + 2] = v.z;
-      x[j + 3] = v.w;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < RD::E; j++) {
-      const uint32_t* p = g + RD::gidx(H, col, RD::row(rbase, j));
-      x[j] = STREAM ? __builtin_nontemporal_load(p) : *p;
-    }
-  }
-}
-
-template <typename RD, bool STREAM = false>
-__device__ __forceinline__ void store_global(const uint32_t (&x)[RD::E], uint32_t* g, int H, int col, int rbase) {
-  if constexpr (RD::VEC) {
-#pragma unroll
-    for (int j = 0; j < RD::E; j += 4) {
-      u32x4 o;
-      o.x = x[j];
-      o.y = x[j + 1];
-      o.z = x[j + 2];
-      o.w = x[j + 3];
-      u32x4* p = reinterpret_cast<u32x4*>(g + RD::gidx(H, col, rbase + j));
-      if constexpr (STREAM)
-        __builtin_nontemporal_store(o, p);
-      else
-        *p = o;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < RD::E; j++) {
-      uint32_t* p = g + RD::gidx(H, col, RD::row(rbase, j));
-      if constexpr (STREAM)
-        __builtin_nontemporal_store(x[j], p);
-      else
-        *p = x[j];
-    }
-  }
-}
-
-template <typename RD, int PAD>
-__device__ __forceinline__ void load_lds(uint32_t (&x)[RD::E], const uint32_t* lds, int c, int rbase) {
-#pragma unroll
-  for (int j = 0; j < RD::E; j++) x[j] = lds[RD::row(rbase, j) * PAD + c];
-}
-
-template <typename RD, int PAD>
-__device__ __forceinline__ void store_lds(const uint32_t (&x)[RD::E], uint32_t* lds, int c, int rbase) {
-#pragma unroll
-  for (int j = 0; j < RD::E; j++) lds[RD::row(rbase, j) * PAD + c] = x[j];
-}
 
 // ------------------------------------------------------------------ plain transform pass
 
@@ -963,131 +652,6 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
     kip_b_body<LOGR, false>(Xe, De, evk_e, acc_e, A, lds, ltw, e, col0, q, minv, T.red[pe], tw, itw);
 }
 
-// ------------------------------------------------------------------ tensor product + pass B of d_2..d_k's INTT
-
-// One tile of one limb of every d_t: the tensor product (four residues per
-// thread and step, tensor4), all k + 1 limbs written as by k_tensor (d_0,
-// d_1 and the digits' own d_t limbs are read in the NTT domain later), and
-// d_2..d_k also kept in LDS, where the first pass of their inverse transform
-// (pass B: both of its rounds, twiddles staged once for the k - 1 limbs)
-// runs before its output is written.  The pass then reads nothing back from
-// HBM.  Tiles of 1024 residues from k = 5; 2048 for k = 3, 4 and 4096 for
-// k = 2, so that the k - 1 tiles' round items (64 per 1024 residues at 256
-// rows per block) still cover the 256 threads.
-template <int LOGR, int K>
-constexpr int tib_lds_words() {
-  return (K - 1) * Geo<LOGR, tib_tile_log(K)>::LDS_WORDS;
-}
-
-template <int LOGR, int K, int TL, bool LAZY>
-__device__ __forceinline__ void tib_rounds(uint32_t* dc, size_t tpoly, uint32_t* lds, const uint2* ltw, int s0,
-                                           int col0, uint32_t q) {
-  using G = Geo<LOGR, TL>;
-  using R1 = Rnd<LOGR, true, false, kThreads, TL>;  // inverse: consecutive round first
-  using R2 = Rnd<LOGR, true, true, kThreads, TL>;
-  const uint4 nf{};
-  for (int it = threadIdx.x; it < (K - 1) * R1::ITEMS; it += kThreads) {
-    const int tt = it / R1::ITEMS;
-    int cc, rb, hi;
-    R1::decode(it - tt * R1::ITEMS, cc, rb, hi);
-    uint32_t x[R1::E];
-    load_lds<R1, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
-    item_bfly_t<R1::RB, false, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, cc}, s0 + R1::SL0, hi, q, nf);
-    store_lds<R1, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
-  }
-  __syncthreads();
-  for (int it = threadIdx.x; it < (K - 1) * R2::ITEMS; it += kThreads) {
-    const int tt = it / R2::ITEMS;
-    int cc, rb, hi;
-    R2::decode(it - tt * R2::ITEMS, cc, rb, hi);
-    uint32_t x[R2::E];
-    load_lds<R2, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
-    item_bfly_t<R2::RB, false, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, cc}, s0 + R2::SL0, hi, q, nf);
-    store_global<R2>(x, dc + (size_t)tt * tpoly, 0, col0 + cc, rb);
-  }
-}
-
-// One tile of limb j: inp the k inputs, wsj the job's workspace with D at
-// d_off ([k+1][level][N]) and the pass-B outputs at dc_off ([k-1][level][N]).
-template <int LOGR, int K>
-__device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], int level, int log_n, int j,
-                                               int tile, uint32_t* wsj, size_t d_off, size_t dc_off,
-                                               const DevTables& T, uint32_t* lds, uint2* ltw) {
-  constexpr int TL = tib_tile_log(K);
-  constexpr int STEPS = 1 << (TL - 10);  // uint4 groups per thread
-  using G = Geo<LOGR, TL>;
-  const size_t N = (size_t)1 << log_n;
-  const int s0 = log_n - LOGR;
-  const int col0 = tile * G::COLS;
-  const uint2* itw = reinterpret_cast<const uint2*>(T.itw) + ((size_t)j << log_n);
-  stage_tw_pass_b<G::COLS, LOGR, kThreads>(ltw, itw, s0, col0);
-  uint32_t* D = wsj + d_off + (size_t)j * N;
-  const size_t tpoly = (size_t)level * N;
-  for (int g = 0; g < STEPS; g++) {
-    const int local = g * kThreads + threadIdx.x;  // uint4 index within the tile
-    const size_t n = (size_t)tile * (STEPS * kThreads) + local;
-    uint4 P[K + 1];
-    tensor4<K>(inp, level, log_n, j, n, T, P);
-#pragma unroll
-    for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(D + (size_t)t * tpoly)[n] = P[t];
-    // residues 4 local .. 4 local + 3: one 2^LOGR-residue block (column c)
-    const int e = 4 * local;
-    const int c = e >> LOGR, r = e & ((1 << LOGR) - 1);
-#pragma unroll
-    for (int t = 2; t <= K; t++) {
-      uint32_t* tl = lds + (t - 2) * G::LDS_WORDS + c;
-      tl[r * G::PAD] = P[t].x;
-      tl[(r + 1) * G::PAD] = P[t].y;
-      tl[(r + 2) * G::PAD] = P[t].z;
-      tl[(r + 3) * G::PAD] = P[t].w;
-    }
-  }
-  __syncthreads();  // d_t tiles and staged twiddles
-  uint32_t* dc = wsj + dc_off + (size_t)j * N;
-  const uint32_t q = T.mod[j];
-  if (q < (1u << 30))
-    tib_rounds<LOGR, K, TL, true>(dc, tpoly, lds, ltw, s0, col0, q);
-  else
-    tib_rounds<LOGR, K, TL, false>(dc, tpoly, lds, ltw, s0, col0, q);
-}
-
-// Grid: (N / 2^tib_tile_log(K) tiles, level limbs, jobs); per job ws_job
-// words of workspace.
-template <int LOGR, int K>
-__global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_job_stride, int level, int log_n,
-                                                        uint32_t* ws, long long ws_job, long long d_off,
-                                                        long long dc_off, DevTables T) {
-  __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
-  __shared__ uint2 ltw[Geo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
-  const size_t job_in = (size_t)blockIdx.z * (size_t)in_job_stride;
-  const uint32_t* inp[K];
-#pragma unroll
-  for (int u = 0; u < K; u++) inp[u] = in.p[u] + job_in;
-  tensor_ib_tile<LOGR, K>(inp, level, log_n, blockIdx.y, blockIdx.x, ws + (size_t)blockIdx.z * (size_t)ws_job,
-                          (size_t)d_off, (size_t)dc_off, T, lds, ltw);
-}
-
-// Job-table form: jobs [j0, j0 + nj) of equal k; blocks per job
-// (N / 2^tib_tile_log(k)) level.  D and the pass-B outputs at their places
-// in the job's workspace (WsLayout).
-template <int LOGR, int K>
-__global__ __launch_bounds__(kThreads) void k_tensor_ib_jt(const JobDesc* jt, int j0, int nj, int log_n,
-                                                           DevTables T) {
-  __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
-  __shared__ uint2 ltw[Geo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
-  const int j = j0 + find_job(jt + j0, nj, S_TENSOR, blockIdx.x);
-  const int local = blockIdx.x - jt[j].blk0[S_TENSOR];
-  const int tiles = 1 << (log_n - tib_tile_log(K));
-  const int level = jt[j].level;
-  if (local >= tiles * level) return;
-  const uint32_t* inp[K];
-#pragma unroll
-  for (int u = 0; u < K; u++) inp[u] = jt[j].in[u];
-  const size_t N = (size_t)1 << log_n;
-  tensor_ib_tile<LOGR, K>(inp, level, log_n, local / tiles, local % tiles, jt[j].ws, 0,
-                          (size_t)(K + 1) * level * N, T, lds, ltw);
-}
-
 // ------------------------------------------------------------------ job-table forms
 
 // One transform pass over the jobs of a table: stage S_INTT_D (d_2..d_k into
@@ -1354,7 +918,7 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
   A.tiles = 1 << (prm->log_n - kModupTileLog);
   A.units = n_jobs * A.groups * A.tiles;
   const unsigned blocks =
-      (unsigned)(((A.units + 7) / 8) * 8 * (modup_two_targets(A.alpha) ? modup_pairs(A.level, A.E) : A.E));
+      (unsigned)(((A.units + 7) / 8) * 8 * (modup_pairs_on(prm) ? modup_pairs(A.level, A.E) : A.E));
   ProfScope ps(P_MODUP, s);
   const DevTables& T = prm->dt;
 #define MICK_MA2(LR, AL) k_modup_a2<LR, AL><<<blocks, kModupThreads, 0, s>>>(dsc, X, A, T)
@@ -1364,7 +928,12 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
     case 1: MICK_MA(LR, 1); break;                                      \
     case 2: MICK_MA(LR, 2); break;                                      \
     case 4: MICK_MA(LR, 4); break;                                      \
-    case 8: MICK_MA2(LR, 8); break;                                     \
+    case 8:                                                             \
+      if (modup_pairs_on(prm))                                          \
+        MICK_MA2(LR, 8);                                                \
+      else                                                              \
+        MICK_MA(LR, 8);                                                 \
+      break;                                                            \
     case 16: MICK_MA(LR, 16); break;                                    \
     case 24: MICK_MA(LR, 24); break;                                    \
     case 32: MICK_MA(LR, 32); break;                                    \
@@ -1379,73 +948,6 @@ int launch_modup_a(const mick_params* prm, const uint32_t* dsc, uint32_t* X, Mod
 #undef MICK_MA
 #undef MICK_MA2
   return hip_error(hipGetLastError(), "modup launch");
-}
-
-int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,
-                     uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs, hipStream_t s) {
-  dim3 grid((unsigned)(prm->N >> tib_tile_log(k)), (unsigned)level, (unsigned)n_jobs);
-  const DevTables& T = prm->dt;
-  const int ln = prm->log_n;
-  ProfScope ps(P_TENSOR_IB, s);
-#define MICK_TIB(LR, KK) \
-  k_tensor_ib<LR, KK><<<grid, kThreads, 0, s>>>(in, in_job_stride, level, ln, ws, ws_job, d_off, dc_off, T)
-#define MICK_TIB_K(LR)                                                   \
-  switch (k) {                                                           \
-    case 2: MICK_TIB(LR, 2); break;                                      \
-    case 3: MICK_TIB(LR, 3); break;                                      \
-    case 4: MICK_TIB(LR, 4); break;                                      \
-    case 5: MICK_TIB(LR, 5); break;                                      \
-    case 6: MICK_TIB(LR, 6); break;                                      \
-    case 7: MICK_TIB(LR, 7); break;                                      \
-    case 8: MICK_TIB(LR, 8); break;                                      \
-    case 9: MICK_TIB(LR, 9); break;                                      \
-    case 10: MICK_TIB(LR, 10); break;                                    \
-    case 11: MICK_TIB(LR, 11); break;                                    \
-    case 12: MICK_TIB(LR, 12); break;                                    \
-    default: return set_error(MICK_E_ARG, "k out of range");            \
-  }
-  switch (prm->split_b) {
-    case 6: MICK_TIB_K(6) break;
-    case 7: MICK_TIB_K(7) break;
-    case 8: MICK_TIB_K(8) break;
-    default: return set_error(MICK_E_ARG, "pass split out of range");
-  }
-#undef MICK_TIB_K
-#undef MICK_TIB
-  return hip_error(hipGetLastError(), "tensor + pass B launch");
-}
-
-int launch_tensor_ib_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks,
-                        hipStream_t s) {
-  if (blocks <= 0) return MICK_OK;
-  const DevTables& T = prm->dt;
-  const int ln = prm->log_n;
-  ProfScope ps(P_TENSOR_IB, s);
-#define MICK_TIB(LR, KK) k_tensor_ib_jt<LR, KK><<<blocks, kThreads, 0, s>>>(jt, j0, nj, ln, T)
-#define MICK_TIB_K(LR)                                                   \
-  switch (k) {                                                           \
-    case 2: MICK_TIB(LR, 2); break;                                      \
-    case 3: MICK_TIB(LR, 3); break;                                      \
-    case 4: MICK_TIB(LR, 4); break;                                      \
-    case 5: MICK_TIB(LR, 5); break;                                      \
-    case 6: MICK_TIB(LR, 6); break;                                      \
-    case 7: MICK_TIB(LR, 7); break;                                      \
-    case 8: MICK_TIB(LR, 8); break;                                      \
-    case 9: MICK_TIB(LR, 9); break;                                      \
-    case 10: MICK_TIB(LR, 10); break;                                    \
-    case 11: MICK_TIB(LR, 11); break;                                    \
-    case 12: MICK_TIB(LR, 12); break;                                    \
-    default: return set_error(MICK_E_ARG, "k out of range");            \
-  }
-  switch (prm->split_b) {
-    case 6: MICK_TIB_K(6) break;
-    case 7: MICK_TIB_K(7) break;
-    case 8: MICK_TIB_K(8) break;
-    default: return set_error(MICK_E_ARG, "pass split out of range");
-  }
-#undef MICK_TIB_K
-#undef MICK_TIB
-  return hip_error(hipGetLastError(), "tensor + pass B launch");
 }
 
 int launch_kip_b(const mick_params* prm, const uint32_t* X, const uint32_t* D, const uint32_t* evk, uint32_t* acc,
@@ -1504,7 +1006,12 @@ int launch_modup_a_jt(const mick_params* prm, const JobDesc* jt, int nj, int blo
     case 1: MICK_MA(LR, 1); break;                                      \
     case 2: MICK_MA(LR, 2); break;                                      \
     case 4: MICK_MA(LR, 4); break;                                      \
-    case 8: MICK_MA2(LR, 8); break;                                     \
+    case 8:                                                             \
+      if (modup_pairs_on(prm))                                          \
+        MICK_MA2(LR, 8);                                                \
+      else                                                              \
+        MICK_MA(LR, 8);                                                 \
+      break;                                                            \
     case 16: MICK_MA(LR, 16); break;                                    \
     case 24: MICK_MA(LR, 24); break;                                    \
     case 32: MICK_MA(LR, 32); break;                                    \

@@ -20,6 +20,11 @@ inline int modup_rows(int alpha) {
 // to 8 primes (one source load feeds both); wider digits leave no registers
 // for a second target, and narrower ones read too few source rows to gain.
 inline bool modup_two_targets(int alpha) { return modup_rows(alpha) == 8; }
+// Whether a parameter set's ModUp launches take two targets per workgroup:
+// digits of 5 to 8 primes, unless set to one target (mick_params_set_modup_targets).
+inline bool modup_pairs_on(const mick_params* prm) {
+  return modup_two_targets(prm->alpha) && prm->modup_targets == 2;
+}
 
 // Workgroups per source tile of the two-target kernel: ceil(level / 2) +
 // ceil(K / 2), an upper bound on the pairs of q targets plus the pairs of
@@ -76,6 +81,152 @@ __device__ __forceinline__ void tensor4(const uint32_t* const (&inp)[K], int lev
     P[t].z = shoup(P[t].z, f, fsh, m);
     P[t].w = shoup(P[t].w, f, fsh, m);
   }
+}
+
+// Ways of forming d_0..d_k (all give the same canonical residues):
+//  kTensorChain  one linear factor at a time (tensor4);
+//  kTensorTree   a balanced binary tree of products of polynomials in Y, each
+//                node's coefficients exact 64-bit sums of products reduced
+//                once (Montgomery);
+//  kTensorFilter the same tree with the fast filtering forms of Sec. II and
+//                Sec. V-A at its nodes: Karatsuba for two linear factors and
+//                for two cubics (two levels), the 3-parallel fast filter for
+//                two quadratics, schoolbook sums elsewhere.
+enum TensorMethod { kTensorChain = 0, kTensorTree = 1, kTensorFilter = 2, kTensorMethods = 3 };
+
+// Montgomery reduction of a sum of `terms` products of canonical residues
+// below m < 2^30: below 4 m^2 < m 2^32 for up to four terms, below 8 m^2 <
+// 2 m 2^32 for up to eight.
+template <int TERMS>
+__device__ __forceinline__ uint32_t redc_terms(uint64_t t, uint32_t m, uint32_t minv) {
+  static_assert(TERMS >= 1 && TERMS <= 8, "at most eight products per sum");
+  if constexpr (TERMS <= 4)
+    return redc(t, m, minv);
+  else
+    return redc_2m(t, m, minv);
+}
+
+__device__ __forceinline__ uint64_t mul64(uint32_t a, uint32_t b) { return (uint64_t)a * b; }
+
+// C = A B for polynomials in Y with canonical coefficients below m < 2^30;
+// every coefficient of C is the exact sum of its products, reduced once, so
+// it carries one factor R^-1.
+template <int NA, int NB, bool FF>
+__device__ __forceinline__ void poly_mul(const uint32_t (&A)[NA], const uint32_t (&B)[NB],
+                                         uint32_t (&C)[NA + NB - 1], uint32_t m, uint32_t minv) {
+  if constexpr (FF && NA == 2 && NB == 2) {
+    // Karatsuba: a0 b1 + a1 b0 = (a0 + a1)(b0 + b1) - a0 b0 - a1 b1
+    const uint64_t lo = mul64(A[0], B[0]), hi = mul64(A[1], B[1]);
+    const uint64_t mid = mul64(A[0] + A[1], B[0] + B[1]) - lo - hi;
+    C[0] = redc_terms<1>(lo, m, minv);
+    C[1] = redc_terms<2>(mid, m, minv);
+    C[2] = redc_terms<1>(hi, m, minv);
+  } else if constexpr (FF && NA == 3 && NB == 3) {
+    // 3-parallel fast filter: six products for the nine of the schoolbook form
+    const uint64_t p0 = mul64(A[0], B[0]), p1 = mul64(A[1], B[1]), p2 = mul64(A[2], B[2]);
+    const uint64_t p01 = mul64(A[0] + A[1], B[0] + B[1]);
+    const uint64_t p12 = mul64(A[1] + A[2], B[1] + B[2]);
+    const uint64_t p012 = mul64(A[0] + A[1] + A[2], B[0] + B[1] + B[2]);  // < 9 m^2
+    C[0] = redc_terms<1>(p0, m, minv);
+    C[1] = redc_terms<2>(p01 - p0 - p1, m, minv);
+    C[2] = redc_terms<3>(p012 + 2 * p1 - p01 - p12, m, minv);  // a0 b2 + a1 b1 + a2 b0
+    C[3] = redc_terms<2>(p12 - p1 - p2, m, minv);
+    C[4] = redc_terms<1>(p2, m, minv);
+  } else if constexpr (FF && NA == 4 && NB == 4) {
+    // Karatsuba on halves A = A0 + Y^2 A1, B = B0 + Y^2 B1, each half product
+    // itself by Karatsuba, all in exact 64-bit sums: A0 B0, A1 B1 and
+    // (A0 + A1)(B0 + B1) (sums of halves below 2m, their sums below 4m)
+    uint64_t lo[3], hi[3], md[3];
+    auto kara = [](uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1, uint64_t (&r)[3]) {
+      r[0] = mul64(a0, b0);
+      r[2] = mul64(a1, b1);
+      r[1] = mul64(a0 + a1, b0 + b1) - r[0] - r[2];
+    };
+    kara(A[0], A[1], B[0], B[1], lo);
+    kara(A[2], A[3], B[2], B[3], hi);
+    kara(A[0] + A[2], A[1] + A[3], B[0] + B[2], B[1] + B[3], md);
+    for (int i = 0; i < 3; i++) md[i] -= lo[i] + hi[i];
+    C[0] = redc_terms<1>(lo[0], m, minv);
+    C[1] = redc_terms<2>(lo[1], m, minv);
+    C[2] = redc_terms<3>(lo[2] + md[0], m, minv);
+    C[3] = redc_terms<4>(md[1], m, minv);
+    C[4] = redc_terms<3>(md[2] + hi[0], m, minv);
+    C[5] = redc_terms<2>(hi[1], m, minv);
+    C[6] = redc_terms<1>(hi[2], m, minv);
+  } else {
+#pragma unroll
+    for (int t = 0; t < NA + NB - 1; t++) {
+      constexpr int kMin = NA < NB ? NA : NB;
+      uint64_t acc = 0;
+#pragma unroll
+      for (int i = 0; i < NA; i++)
+        if (t - i >= 0 && t - i < NB) acc += mul64(A[i], B[t - i]);
+      C[t] = redc_terms<kMin>(acc, m, minv);
+    }
+  }
+}
+
+// prod_{u in [U0, U1)} (c0^u + c1^u Y) by a balanced binary tree: the left
+// half of the factors times the right half, recursively.  Every internal
+// node adds one factor R^-1, so the root carries R^-(U1 - U0 - 1).
+template <int U0, int U1, bool FF>
+struct TensorTree {
+  static constexpr int N = U1 - U0;
+  static constexpr int H = (N + 1) / 2;
+  template <int K>
+  __device__ static void run(const uint32_t (&a)[K], const uint32_t (&b)[K], uint32_t (&P)[N + 1], uint32_t m,
+                             uint32_t minv) {
+    if constexpr (N == 1) {
+      P[0] = a[U0];
+      P[1] = b[U0];
+    } else {
+      uint32_t L[H + 1], R[N - H + 1];
+      TensorTree<U0, U0 + H, FF>::run(a, b, L, m, minv);
+      TensorTree<U0 + H, U1, FF>::run(a, b, R, m, minv);
+      poly_mul<H + 1, N - H + 1, FF>(L, R, P, m, minv);
+    }
+  }
+};
+
+// The tensor product of tensor4 by the product tree (FF: fast filtering
+// nodes); same inputs, same canonical outputs.
+template <int K, bool FF>
+__device__ __forceinline__ void tensor4_tree(const uint32_t* const (&inp)[K], int level, int log_n, int j, size_t n,
+                                             const DevTables& T, uint4 (&P)[K + 1]) {
+  const size_t N = (size_t)1 << log_n;
+  const uint32_t m = T.mod[j], minv = T.minv[j];
+  const size_t limb = (size_t)j * N;
+  const size_t poly = (size_t)level * N;
+  uint4 a4[K], b4[K];
+#pragma unroll
+  for (int u = 0; u < K; u++) {
+    a4[u] = reinterpret_cast<const uint4*>(inp[u] + limb)[n];
+    b4[u] = reinterpret_cast<const uint4*>(inp[u] + poly + limb)[n];
+  }
+  const uint32_t* rp = T.rpow + (size_t)j * 2 * (kMaxK + 1);
+  const uint32_t f = rp[2 * (K - 1)], fsh = rp[2 * (K - 1) + 1];
+  uint32_t a[K], b[K], r[K + 1];
+#define MICK_TREE_LANE(C)                                        \
+  for (int u = 0; u < K; u++) {                                  \
+    a[u] = a4[u].C;                                              \
+    b[u] = b4[u].C;                                              \
+  }                                                              \
+  TensorTree<0, K, FF>::run(a, b, r, m, minv);                   \
+  for (int t = 0; t <= K; t++) P[t].C = shoup(r[t], f, fsh, m);
+  MICK_TREE_LANE(x)
+  MICK_TREE_LANE(y)
+  MICK_TREE_LANE(z)
+  MICK_TREE_LANE(w)
+#undef MICK_TREE_LANE
+}
+
+template <int K, int TM>
+__device__ __forceinline__ void tensor4_by(const uint32_t* const (&inp)[K], int level, int log_n, int j, size_t n,
+                                           const DevTables& T, uint4 (&P)[K + 1]) {
+  if constexpr (TM == kTensorChain)
+    tensor4<K>(inp, level, log_n, j, n, T, P);
+  else
+    tensor4_tree<K, TM == kTensorFilter>(inp, level, log_n, j, n, T, P);
 }
 
 struct ModupArgs {

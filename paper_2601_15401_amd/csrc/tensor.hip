@@ -1,0 +1,212 @@
+// The tensor product of eq. (d_u formula for n-ct mult) fused with the first
+// pass (pass B) of the inverse transform of d_2..d_k, same-shape and
+// job-table launches.
+#include "ntt_core.h"
+
+namespace mick {
+
+namespace {
+
+// ------------------------------------------------------------------ tensor product + pass B of d_2..d_k's INTT
+
+// One tile of one limb of every d_t: the tensor product (four residues per
+// thread and step, tensor4), all k + 1 limbs written as by k_tensor (d_0,
+// d_1 and the digits' own d_t limbs are read in the NTT domain later), and
+// d_2..d_k also kept in LDS, where the first pass of their inverse transform
+// (pass B: both of its rounds, twiddles staged once for the k - 1 limbs)
+// runs before its output is written.  The pass then reads nothing back from
+// HBM.  Tiles of 1024 residues from k = 5; 2048 for k = 3, 4 and 4096 for
+// k = 2, so that the k - 1 tiles' round items (64 per 1024 residues at 256
+// rows per block) still cover the 256 threads.
+template <int LOGR, int K>
+constexpr int tib_lds_words() {
+  return (K - 1) * Geo<LOGR, tib_tile_log(K)>::LDS_WORDS;
+}
+
+template <int LOGR, int K, int TL, bool LAZY>
+__device__ __forceinline__ void tib_rounds(uint32_t* dc, size_t tpoly, uint32_t* lds, const uint2* ltw, int s0,
+                                           int col0, uint32_t q) {
+  using G = Geo<LOGR, TL>;
+  using R1 = Rnd<LOGR, true, false, kThreads, TL>;  // inverse: consecutive round first
+  using R2 = Rnd<LOGR, true, true, kThreads, TL>;
+  const uint4 nf{};
+  for (int it = threadIdx.x; it < (K - 1) * R1::ITEMS; it += kThreads) {
+    const int tt = it / R1::ITEMS;
+    int cc, rb, hi;
+    R1::decode(it - tt * R1::ITEMS, cc, rb, hi);
+    uint32_t x[R1::E];
+    load_lds<R1, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
+    item_bfly_t<R1::RB, false, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, cc}, s0 + R1::SL0, hi, q, nf);
+    store_lds<R1, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < (K - 1) * R2::ITEMS; it += kThreads) {
+    const int tt = it / R2::ITEMS;
+    int cc, rb, hi;
+    R2::decode(it - tt * R2::ITEMS, cc, rb, hi);
+    uint32_t x[R2::E];
+    load_lds<R2, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
+    item_bfly_t<R2::RB, false, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, cc}, s0 + R2::SL0, hi, q, nf);
+    store_global<R2>(x, dc + (size_t)tt * tpoly, 0, col0 + cc, rb);
+  }
+}
+
+// One tile of limb j: inp the k inputs, wsj the job's workspace with D at
+// d_off ([k+1][level][N]) and the pass-B outputs at dc_off ([k-1][level][N]).
+template <int LOGR, int K, int TM>
+__device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], int level, int log_n, int j,
+                                               int tile, uint32_t* wsj, size_t d_off, size_t dc_off,
+                                               const DevTables& T, uint32_t* lds, uint2* ltw) {
+  constexpr int TL = tib_tile_log(K);
+  constexpr int STEPS = 1 << (TL - 10);  // uint4 groups per thread
+  using G = Geo<LOGR, TL>;
+  const size_t N = (size_t)1 << log_n;
+  const int s0 = log_n - LOGR;
+  const int col0 = tile * G::COLS;
+  const uint2* itw = reinterpret_cast<const uint2*>(T.itw) + ((size_t)j << log_n);
+  stage_tw_pass_b<G::COLS, LOGR, kThreads>(ltw, itw, s0, col0);
+  uint32_t* D = wsj + d_off + (size_t)j * N;
+  const size_t tpoly = (size_t)level * N;
+  for (int g = 0; g < STEPS; g++) {
+    const int local = g * kThreads + threadIdx.x;  // uint4 index within the tile
+    const size_t n = (size_t)tile * (STEPS * kThreads) + local;
+    uint4 P[K + 1];
+    tensor4_by<K, TM>(inp, level, log_n, j, n, T, P);
+#pragma unroll
+    for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(D + (size_t)t * tpoly)[n] = P[t];
+    // residues 4 local .. 4 local + 3: one 2^LOGR-residue block (column c)
+    const int e = 4 * local;
+    const int c = e >> LOGR, r = e & ((1 << LOGR) - 1);
+#pragma unroll
+    for (int t = 2; t <= K; t++) {
+      uint32_t* tl = lds + (t - 2) * G::LDS_WORDS + c;
+      tl[r * G::PAD] = P[t].x;
+      tl[(r + 1) * G::PAD] = P[t].y;
+      tl[(r + 2) * G::PAD] = P[t].z;
+      tl[(r + 3) * G::PAD] = P[t].w;
+    }
+  }
+  __syncthreads();  // d_t tiles and staged twiddles
+  uint32_t* dc = wsj + dc_off + (size_t)j * N;
+  const uint32_t q = T.mod[j];
+  if (q < (1u << 30))
+    tib_rounds<LOGR, K, TL, true>(dc, tpoly, lds, ltw, s0, col0, q);
+  else
+    tib_rounds<LOGR, K, TL, false>(dc, tpoly, lds, ltw, s0, col0, q);
+}
+
+// Grid: (N / 2^tib_tile_log(K) tiles, level limbs, jobs); per job ws_job
+// words of workspace.
+template <int LOGR, int K, int TM>
+__global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_job_stride, int level, int log_n,
+                                                        uint32_t* ws, long long ws_job, long long d_off,
+                                                        long long dc_off, DevTables T) {
+  __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
+  __shared__ uint2 ltw[Geo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
+  const size_t job_in = (size_t)blockIdx.z * (size_t)in_job_stride;
+  const uint32_t* inp[K];
+#pragma unroll
+  for (int u = 0; u < K; u++) inp[u] = in.p[u] + job_in;
+  tensor_ib_tile<LOGR, K, TM>(inp, level, log_n, blockIdx.y, blockIdx.x, ws + (size_t)blockIdx.z * (size_t)ws_job,
+                          (size_t)d_off, (size_t)dc_off, T, lds, ltw);
+}
+
+// Job-table form: jobs [j0, j0 + nj) of equal k; blocks per job
+// (N / 2^tib_tile_log(k)) level.  D and the pass-B outputs at their places
+// in the job's workspace (WsLayout).
+template <int LOGR, int K, int TM>
+__global__ __launch_bounds__(kThreads) void k_tensor_ib_jt(const JobDesc* jt, int j0, int nj, int log_n,
+                                                           DevTables T) {
+  __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
+  __shared__ uint2 ltw[Geo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
+  const int j = j0 + find_job(jt + j0, nj, S_TENSOR, blockIdx.x);
+  const int local = blockIdx.x - jt[j].blk0[S_TENSOR];
+  const int tiles = 1 << (log_n - tib_tile_log(K));
+  const int level = jt[j].level;
+  if (local >= tiles * level) return;
+  const uint32_t* inp[K];
+#pragma unroll
+  for (int u = 0; u < K; u++) inp[u] = jt[j].in[u];
+  const size_t N = (size_t)1 << log_n;
+  tensor_ib_tile<LOGR, K, TM>(inp, level, log_n, local / tiles, local % tiles, jt[j].ws, 0,
+                          (size_t)(K + 1) * level * N, T, lds, ltw);
+}
+
+}  // namespace
+
+// The tensor-product form (rns.h TensorMethod) is a template parameter of
+// the fused kernels, chosen per parameter set (mick_params_set_tensor_method).
+#define MICK_TIB_TM(LR, KK, KERNEL, ARGS, GRID)                                     \
+  switch (prm->tensor_method) {                                                     \
+    case kTensorTree: KERNEL<LR, KK, kTensorTree><<<GRID, kThreads, 0, s>>> ARGS; break;     \
+    case kTensorFilter: KERNEL<LR, KK, kTensorFilter><<<GRID, kThreads, 0, s>>> ARGS; break; \
+    default: KERNEL<LR, KK, kTensorChain><<<GRID, kThreads, 0, s>>> ARGS; break;           \
+  }
+
+int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,
+                     uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs, hipStream_t s) {
+  dim3 grid((unsigned)(prm->N >> tib_tile_log(k)), (unsigned)level, (unsigned)n_jobs);
+  const DevTables& T = prm->dt;
+  const int ln = prm->log_n;
+  ProfScope ps(P_TENSOR_IB, s);
+#define MICK_TIB(LR, KK) MICK_TIB_TM(LR, KK, k_tensor_ib, (in, in_job_stride, level, ln, ws, ws_job, d_off, dc_off, T), grid)
+#define MICK_TIB_K(LR)                                                   \
+  switch (k) {                                                           \
+    case 2: MICK_TIB(LR, 2); break;                                      \
+    case 3: MICK_TIB(LR, 3); break;                                      \
+    case 4: MICK_TIB(LR, 4); break;                                      \
+    case 5: MICK_TIB(LR, 5); break;                                      \
+    case 6: MICK_TIB(LR, 6); break;                                      \
+    case 7: MICK_TIB(LR, 7); break;                                      \
+    case 8: MICK_TIB(LR, 8); break;                                      \
+    case 9: MICK_TIB(LR, 9); break;                                      \
+    case 10: MICK_TIB(LR, 10); break;                                    \
+    case 11: MICK_TIB(LR, 11); break;                                    \
+    case 12: MICK_TIB(LR, 12); break;                                    \
+    default: return set_error(MICK_E_ARG, "k out of range");            \
+  }
+  switch (prm->split_b) {
+    case 6: MICK_TIB_K(6) break;
+    case 7: MICK_TIB_K(7) break;
+    case 8: MICK_TIB_K(8) break;
+    default: return set_error(MICK_E_ARG, "pass split out of range");
+  }
+#undef MICK_TIB_K
+#undef MICK_TIB
+  return hip_error(hipGetLastError(), "tensor + pass B launch");
+}
+
+int launch_tensor_ib_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks,
+                        hipStream_t s) {
+  if (blocks <= 0) return MICK_OK;
+  const DevTables& T = prm->dt;
+  const int ln = prm->log_n;
+  ProfScope ps(P_TENSOR_IB, s);
+#define MICK_TIB(LR, KK) MICK_TIB_TM(LR, KK, k_tensor_ib_jt, (jt, j0, nj, ln, T), blocks)
+#define MICK_TIB_K(LR)                                                   \
+  switch (k) {                                                           \
+    case 2: MICK_TIB(LR, 2); break;                                      \
+    case 3: MICK_TIB(LR, 3); break;                                      \
+    case 4: MICK_TIB(LR, 4); break;                                      \
+    case 5: MICK_TIB(LR, 5); break;                                      \
+    case 6: MICK_TIB(LR, 6); break;                                      \
+    case 7: MICK_TIB(LR, 7); break;                                      \
+    case 8: MICK_TIB(LR, 8); break;                                      \
+    case 9: MICK_TIB(LR, 9); break;                                      \
+    case 10: MICK_TIB(LR, 10); break;                                    \
+    case 11: MICK_TIB(LR, 11); break;                                    \
+    case 12: MICK_TIB(LR, 12); break;                                    \
+    default: return set_error(MICK_E_ARG, "k out of range");            \
+  }
+  switch (prm->split_b) {
+    case 6: MICK_TIB_K(6) break;
+    case 7: MICK_TIB_K(7) break;
+    case 8: MICK_TIB_K(8) break;
+    default: return set_error(MICK_E_ARG, "pass split out of range");
+  }
+#undef MICK_TIB_K
+#undef MICK_TIB
+  return hip_error(hipGetLastError(), "tensor + pass B launch");
+}
+
+}  // namespace mick

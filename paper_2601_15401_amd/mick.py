@@ -53,6 +53,7 @@ _SIGS = {
     "mick_mul_relin_rescale_batch": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
                                                     _vp, ctypes.c_size_t, _vp]),
     "mick_ntt": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
+    "mick_bconv": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp]),
     "mick_jobs_workspace_bytes": (ctypes.c_size_t, [_vp, _vp, ctypes.c_int]),
     "mick_mul_relin_rescale_jobs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t, _vp]),
     "mick_jobs_plan": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t, _vp,
@@ -80,6 +81,11 @@ _SIGS = {
     "mick_autotune": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "mick_params_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
     "mick_params_schedule": (ctypes.c_int, [_vp]),
+    "mick_params_set_tensor_method": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "mick_params_set_modup_targets": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "mick_params_modup_targets": (ctypes.c_int, [_vp]),
+    "mick_autotune_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _c_dblp]),
+    "mick_params_tensor_method": (ctypes.c_int, [_vp]),
     "mick_set_allocator": (ctypes.c_int, [_vp, _vp, _vp]),
     "mick_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "mick_profile_select": (ctypes.c_int, [ctypes.c_char_p]),
@@ -449,6 +455,27 @@ def ntt(prm: Params, data: torch.Tensor, first_prime: int, inverse: bool = False
     return data
 
 
+BCONV_VALU, BCONV_MFMA = 0, 1
+
+
+def bconv(prm: Params, src: torch.Tensor, level: int, digit: int, method: int = BCONV_VALU, out=None):
+    """Fast basis conversion of digit `digit` at `level` for src [n_polys, na, N]
+    (coefficient domain); returns [n_polys, level + K - na, N]."""
+    if src.dim() != 3 or src.shape[2] != prm.N:
+        raise ValueError("src must be [n_polys, na, N]")
+    lo = digit * prm.alpha
+    na = max(0, min(prm.alpha, level - lo))
+    n_polys = src.shape[0]
+    if src.shape[1] != na:
+        raise ValueError("src holds %d limbs; digit %d at level %d has %d" % (src.shape[1], digit, level, na))
+    T = level + prm.K - na
+    if out is None:
+        out = _dev_empty(n_polys, T, prm.N)
+    _check(load().mick_bconv(prm.handle, _ptr(src, n_polys * na * prm.N, "src"), n_polys, level, digit,
+                             _ptr(out, n_polys * T * prm.N, "out"), method, _stream()), "mick_bconv")
+    return out
+
+
 def profile_enable(on: bool = True):
     """Bracket every library kernel launch with HIP events on its stream."""
     _check(load().mick_profile_enable(int(on)), "mick_profile_enable")
@@ -572,6 +599,43 @@ def autotune(prm: Params, cache_path: str | None = None) -> int:
 
 def set_schedule(prm: Params, first_pass_log: int):
     _check(load().mick_params_set_schedule(prm.handle, first_pass_log), "mick_params_set_schedule")
+
+
+TENSOR_CHAIN, TENSOR_TREE, TENSOR_FILTER = 0, 1, 2
+
+
+def set_tensor_method(prm: Params, method: int):
+    _check(load().mick_params_set_tensor_method(prm.handle, method), "mick_params_set_tensor_method")
+
+
+def set_modup_targets(prm: Params, targets: int):
+    _check(load().mick_params_set_modup_targets(prm.handle, targets), "mick_params_set_modup_targets")
+
+
+def modup_targets(prm: Params) -> int:
+    m = load().mick_params_modup_targets(prm.handle)
+    if m < 0:
+        raise MickError(m, "mick_params_modup_targets")
+    return m
+
+
+def autotune_report(prm: Params):
+    """[((first-pass log, tensor method, ModUp targets), us per multiply)] of the
+    last timing run of mick_autotune on these parameters."""
+    n = 64
+    cfg = (ctypes.c_int * (3 * n))()
+    us = (ctypes.c_double * n)()
+    m = load().mick_autotune_report(prm.handle, n, cfg, us)
+    if m < 0:
+        raise MickError(m, "mick_autotune_report")
+    return [((cfg[3 * i], cfg[3 * i + 1], cfg[3 * i + 2]), us[i]) for i in range(min(m, n))]
+
+
+def tensor_method(prm: Params) -> int:
+    m = load().mick_params_tensor_method(prm.handle)
+    if m < 0:
+        raise MickError(m, "mick_params_tensor_method")
+    return m
 
 
 def schedule(prm: Params) -> int:

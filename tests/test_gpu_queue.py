@@ -134,19 +134,41 @@ def test_alternative_schedules_are_exact(ln, L, K, dnum):
 
 
 def test_autotune_cache(tmp_path):
+    """Every (split, tensor method, ModUp targets) combination is timed on the
+    whole multiply; the choice is recorded in the cache and reused."""
     path = str(tmp_path / "schedules.txt")
     prm = mick.Params(15, 16, 4, 4)
     a = mick.autotune(prm, path)
     assert a in (7, 8)
+    table = mick.autotune_report(prm)
+    # two splits x three tensor methods x one target (digits of 4 primes)
+    assert sorted(c for c, _ in table) == [(s, t, 1) for s in (7, 8) for t in (0, 1, 2)]
+    best = min(table, key=lambda x: x[1])[0]
+    assert (mick.schedule(prm), mick.tensor_method(prm), mick.modup_targets(prm)) == best
     lines = open(path).read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("mick-schedule ")
-    assert int(lines[0].split()[-2]) == a
+    assert len(lines) == 1 and lines[0].startswith("mick-tune ")
+    assert tuple(int(v) for v in lines[0].split()[-4:-1]) == best
     prm2 = mick.Params(15, 16, 4, 4)
-    assert mick.autotune(prm2, path) == a  # from the cache: nothing appended
+    assert mick.autotune(prm2, path) == a  # from the cache: nothing appended, nothing timed
+    assert (mick.schedule(prm2), mick.tensor_method(prm2), mick.modup_targets(prm2)) == best
+    assert mick.autotune_report(prm2) == []
     assert len(open(path).read().splitlines()) == 1
-    prm3 = mick.Params(16, 32, 8, 4)  # one schedule only: no timing, no entry
+    prm3 = mick.Params(16, 32, 8, 4)  # one split; three tensor methods x one or two ModUp targets
     assert mick.autotune(prm3, path) == 8
-    assert len(open(path).read().splitlines()) == 1
+    assert sorted(c for c, _ in mick.autotune_report(prm3)) == [(8, t, m) for t in (0, 1, 2) for m in (1, 2)]
+    assert len(open(path).read().splitlines()) == 2
+    # the chosen settings change nothing in the result
+    keys = mick.Keys(prm3, 5, 3)
+    rng = np.random.default_rng(3)
+    cts = [_rand_ct(rng, prm3.q[:6], prm3.N) for _ in range(3)]
+    got = mick.mul_relin_rescale(prm3, keys, cts, 6)
+    for t in (0, 1, 2):
+        for m in (1, 2):
+            mick.set_tensor_method(prm3, t)
+            mick.set_modup_targets(prm3, m)
+            assert torch.equal(mick.mul_relin_rescale(prm3, keys, cts, 6), got), (t, m)
+    with pytest.raises(mick.MickError):
+        mick.set_modup_targets(prm, 2)  # digits of four primes take one target
 
 
 def test_torch_allocator_holds_keys():
