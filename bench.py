@@ -45,6 +45,8 @@ WORKLOADS = {
     "mixed512": None,  # heterogeneous batch, see run_mixed
     "serve5000": None,  # open-loop serving, see run_serve
     "trees": None,  # flat / planned tree / binary tree of two-input multiplies, see run_trees
+    "tensor_methods": None,  # the three forms of the tensor product at the three workload shapes
+    "bconv": None,  # the standalone basis conversion on the vector ALUs and on the int8 matrix cores
 }
 # parameter sets of the mixed workload: log_n -> (L, K, dnum)
 MIXED_PARAMS = {13: (3, 1, 3), 14: (8, 2, 4), 15: (16, 4, 4), 16: (32, 8, 4)}
@@ -601,6 +603,113 @@ def serve_leg(args, torch, mick, n_req, loads):
     return leg
 
 
+def run_tensor_methods(args, torch, mick):
+    """The fused multiply with each tensor-product method (chain of linear
+    factors, balanced product tree, tree with fast-filtering nodes) at the
+    three workload shapes: the fused tensor kernel's average duration (HIP
+    events around it) and the whole batched step, medians over three
+    interleaved rounds; every method's outputs are checked equal."""
+    names = {0: "chain", 1: "tree", 2: "tree+fast filtering"}
+    table = []
+    for wl in ("n13_k3", "n15_k4_b16", "n16_k8_b8"):
+        log_n, L, K, dnum, k, level, jobs = WORKLOADS[wl]
+        prm = mick.Params(log_n, L, K, dnum)
+        keys = mick.Keys(prm, 7, k)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(7)
+        q = torch.tensor(prm.q[:level], dtype=torch.int64, device="cuda").view(1, 1, 1, level, 1)
+        cts = (torch.randint(0, 1 << 62, (jobs, k, 2, level, prm.N), generator=gen, device="cuda",
+                             dtype=torch.int64) % q).to(torch.int32)
+        ws = mick.batch_workspace(prm, jobs, k, level)
+        out = torch.empty(jobs, 2, level - k + 1, prm.N, dtype=torch.int32, device="cuda")
+        ref = None
+        stream = torch.cuda.current_stream()
+        step, kern = {m: [] for m in names}, {m: [] for m in names}
+        for rnd in range(3):
+            for m in names:
+                mick.set_tensor_method(prm, m)
+                for _ in range(max(1, args.warmup)):
+                    mick.mul_relin_rescale_batch(prm, keys, cts, level, out=out, ws=ws)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = out.clone()
+                assert torch.equal(out, ref), "tensor method %d differs" % m
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(args.steps):
+                    mick.mul_relin_rescale_batch(prm, keys, cts, level, out=out, ws=ws)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                step[m].append(e0.elapsed_time(e1) / args.steps)
+                mick.profile_select(["tensor_inttB"])
+                mick.profile_enable(True)
+                for _ in range(args.steps):
+                    mick.mul_relin_rescale_batch(prm, keys, cts, level, out=out, ws=ws)
+                torch.cuda.synchronize()
+                t_ms, cnt = mick.profile_collect()["tensor_inttB"]
+                mick.profile_enable(False)
+                mick.profile_select(None)
+                kern[m].append(t_ms / cnt * 1e3)
+        for m in names:
+            st_ms, k_us = float(np.median(step[m])), float(np.median(kern[m]))
+            row = {"workload": wl, "method": names[m], "tensor_kernel_us": round(k_us, 2),
+                   "step_ms": round(st_ms, 4), "ct_mults_per_s": round(jobs / (st_ms / 1e3), 1)}
+            log("  %-11s %-20s tensor kernel %8.2f us   step %8.4f ms   %9.1f ct-mults/s"
+                % (wl, names[m], k_us, st_ms, row["ct_mults_per_s"]))
+            table.append(row)
+        mick.set_tensor_method(prm, 0)
+        del cts, ws, out, ref
+        torch.cuda.empty_cache()
+    print(json.dumps({"tensor_methods": table}), flush=True)
+
+
+def run_bconv(args, torch, mick):
+    """The standalone fast basis conversion, 64-bit multiply-adds on the vector
+    ALUs against the int8 matrix cores, on the ModUp volume of one digit of a
+    batched step: (k - 1) x batch polynomials of the eight-input and
+    four-input workloads.  Medians over three interleaved rounds of HIP
+    events; both forms' outputs are checked equal."""
+    rows = []
+    for wl, digit in (("n16_k8_b8", 0), ("n16_k8_b8", 3), ("n15_k4_b16", 1)):
+        log_n, L, K, dnum, k, level, jobs = WORKLOADS[wl]
+        prm = mick.Params(log_n, L, K, dnum)
+        na = min(prm.alpha, level - digit * prm.alpha)
+        polys = (k - 1) * jobs
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(11)
+        qs = torch.tensor(prm.q[digit * prm.alpha:digit * prm.alpha + na], dtype=torch.int64,
+                          device="cuda").view(1, na, 1)
+        src = (torch.randint(0, 1 << 62, (polys, na, prm.N), generator=gen, device="cuda", dtype=torch.int64)
+               % qs).to(torch.int32)
+        outs = [mick.bconv(prm, src, level, digit, m) for m in (0, 1)]
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0], outs[1]), "the two forms differ"
+        T = outs[0].shape[1]
+        stream = torch.cuda.current_stream()
+        times = {0: [], 1: []}
+        for _ in range(3):
+            for m in (0, 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(args.steps):
+                    mick.bconv(prm, src, level, digit, m, out=outs[m])
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times[m].append(e0.elapsed_time(e1) / args.steps * 1e3)
+        for m, name in ((0, "valu"), (1, "mfma_i8")):
+            us = float(np.median(times[m]))
+            elems = polys * T * prm.N
+            rows.append({"workload": wl, "digit": digit, "digit_primes": na, "targets": T, "polys": polys,
+                         "method": name, "us_per_launch": round(us, 2),
+                         "ns_per_1k_outputs": round(us * 1e3 / (elems / 1e3), 3),
+                         "hbm_gbs": round((polys * (na + T) * prm.N * 4) / (us * 1e-6) / 1e9, 1)})
+            log("  %-11s digit %d (%d primes -> %d targets, %d polys)  %-8s %9.2f us   %7.1f GB/s"
+                % (wl, digit, na, T, polys, name, us, rows[-1]["hbm_gbs"]))
+        del src, outs
+        torch.cuda.empty_cache()
+    print(json.dumps({"bconv": rows}), flush=True)
+
+
 def relin_transforms(k, level, mu, K, alpha):
     """(I)NTT limb transforms of one relinearise-and-rescale of a degree-k
     product at `level` with mu rescales: INTT of d_2..d_k, NTT of the ModUp
@@ -776,9 +885,20 @@ def main():
     if args.workload == "trees":
         run_trees(args, torch, mick)
         return
+    if args.workload == "tensor_methods":
+        run_tensor_methods(args, torch, mick)
+        return
+    if args.workload == "bconv":
+        run_bconv(args, torch, mick)
+        return
     log_n, L, K, dnum, k, level, jobs = WORKLOADS[args.workload]
-    log("params N=2^%d L=%d K=%d dnum=%d; keygen k_max=%d ..." % (log_n, L, K, dnum, k))
+    log("params N=2^%d L=%d K=%d dnum=%d; autotune; keygen k_max=%d ..." % (log_n, L, K, dnum, k))
     prm = mick.Params(log_n, L, K, dnum)
+    mick.autotune(prm)
+    tuning = {"first_pass_log": mick.schedule(prm), "tensor_method": mick.tensor_method(prm),
+              "modup_targets": mick.modup_targets(prm),
+              "table_us_per_mult": {"%d/%d/%d" % c: round(us, 1) for c, us in mick.autotune_report(prm)}}
+    log("autotuned (first-pass log, tensor method, ModUp targets): %s" % str(tuning))
     keys = mick.Keys(prm, 3, k)
     N = prm.N
     scale = 2.0 ** 30
@@ -913,6 +1033,7 @@ def main():
         "config": {"workload": "%d-input multiply, N=2^%d, %d+%d primes, dnum=%d, level %d, batch %d"
                                % (k, log_n, L, K, dnum, level, jobs),
                    "k": k, "log_n": log_n, "level": level, "batch": jobs, "parallelism": "none"},
+        "tuning": tuning,
         "plain": plain,
         "batched_over_plain": round(value / plain["value"], 3) if plain else None,
         **({"unfused": unfused} if unfused else {}),
