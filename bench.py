@@ -865,6 +865,8 @@ def main():
                     help="default workload: skip the mixed-batch and serving legs")
     ap.add_argument("--mixed-steps", type=int, default=5, help="default workload: graph replays of the mixed batch")
     ap.add_argument("--serve-requests", type=int, default=2000, help="default workload: requests of the serving leg")
+    ap.add_argument("--settings", default="", metavar="A/T/M",
+                    help="skip the autotuner: first-pass log A, tensor method T, ModUp targets M (e.g. 8/0/2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized buffer once before timing (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -892,13 +894,24 @@ def main():
         run_bconv(args, torch, mick)
         return
     log_n, L, K, dnum, k, level, jobs = WORKLOADS[args.workload]
-    log("params N=2^%d L=%d K=%d dnum=%d; autotune; keygen k_max=%d ..." % (log_n, L, K, dnum, k))
     prm = mick.Params(log_n, L, K, dnum)
-    mick.autotune(prm)
+    if args.settings:
+        # fixed settings instead of the autotuner: profiler runs that must
+        # see the same kernels from one run to the next
+        a, tm, mt = (int(v) for v in args.settings.split("/"))
+        log("params N=2^%d L=%d K=%d dnum=%d; settings %s; keygen k_max=%d ..." % (log_n, L, K, dnum, args.settings, k))
+        mick.set_schedule(prm, a)
+        mick.set_tensor_method(prm, tm)
+        mick.set_modup_targets(prm, mt)
+        table = {}
+    else:
+        log("params N=2^%d L=%d K=%d dnum=%d; autotune; keygen k_max=%d ..." % (log_n, L, K, dnum, k))
+        mick.autotune(prm)
+        table = {"%d/%d/%d" % c: round(us, 1) for c, us in mick.autotune_report(prm)}
     tuning = {"first_pass_log": mick.schedule(prm), "tensor_method": mick.tensor_method(prm),
-              "modup_targets": mick.modup_targets(prm),
-              "table_us_per_mult": {"%d/%d/%d" % c: round(us, 1) for c, us in mick.autotune_report(prm)}}
-    log("autotuned (first-pass log, tensor method, ModUp targets): %s" % str(tuning))
+              "modup_targets": mick.modup_targets(prm), "autotuned": not args.settings,
+              "table_us_per_mult": table}
+    log("settings (first-pass log, tensor method, ModUp targets): %s" % str(tuning))
     keys = mick.Keys(prm, 3, k)
     N = prm.N
     scale = 2.0 ** 30
@@ -923,15 +936,20 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy of %d MiB done" % args.copy_calibration)
         del a, b
-    log("warmup %d steps (every launch timed) ..." % args.warmup)
+    log("warmup %d steps (every launch timed after the first step) ..." % args.warmup)
     mick.profile_select(None)
-    mick.profile_enable(True)
-    for _ in range(args.warmup):
+    # the first step's launches include loading each kernel's code: that
+    # step is not profiled (unless it is the only warmup step)
+    cold = 1 if args.warmup > 1 else 0
+    for w in range(args.warmup):
+        if w == cold:
+            torch.cuda.synchronize()
+            mick.profile_enable(True)
         mick.mul_relin_rescale_batch(prm, keys, cts, level, out=out, ws=ws)
     torch.cuda.synchronize()
     # the dominant kernel from the warmup; the timed steps record events
     # around that kernel only, so the other launches run back to back
-    dominant = roofline(mick.profile_collect(), args.warmup, N, k, level, K, prm.alpha, jobs)["kernel"]
+    dominant = roofline(mick.profile_collect(), args.warmup - cold, N, k, level, K, prm.alpha, jobs)["kernel"]
     mick.profile_select([dominant])
 
     log("timing %d batched steps ..." % args.steps)

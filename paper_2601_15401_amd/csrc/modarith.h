@@ -60,6 +60,14 @@ __device__ __forceinline__ uint32_t redc_2m(uint64_t T, uint32_t m, uint32_t min
   return hi < mh ? r + m : red1(r, m);
 }
 
+// Montgomery reduction of T < 2m 2^32 left lazy: T 2^-32 mod m as a value in
+// (0, 3m), below 2^32 for m < 2^30.  With u = lo m^-1 mod 2^32 the low word
+// of u m equals lo, so (T - u m) / 2^32 = hi - mh lies in (-m, 2m).
+__device__ __forceinline__ uint32_t redc_lazy(uint64_t T, uint32_t m, uint32_t minv) {
+  const uint32_t lo = (uint32_t)T, hi = (uint32_t)(T >> 32);
+  return hi + m - __umulhi(lo * minv, m);
+}
+
 // (hi, lo) += a * b on a 96-bit accumulator: one 32x32+64-bit multiply-add
 // whose carry-out goes to a lane mask, and one add of that carry into hi.
 __device__ __forceinline__ void mac96(uint64_t& lo, uint32_t& hi, uint32_t a, uint32_t b) {

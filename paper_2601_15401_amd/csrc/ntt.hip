@@ -41,7 +41,7 @@ __device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, ui
   constexpr bool STAGED = FWD && !PASSB;
   constexpr bool STAGED_B = !FWD && PASSB && LOGR == 8;
   if constexpr (STAGED) stage_tw_pass_a<LOGR>(ltwa, tw);
-  if constexpr (STAGED_B) stage_tw_pass_b<G::COLS, G::RB0, kThreads>(ltwa, tw, s0, col0);
+  if constexpr (STAGED_B) stage_tw_pass_b<G::COLS, G::RB0, kThreads, G::RB0>(ltwa, tw, s0, col0);
 #pragma unroll
   for (int i = 0; i < R1::NI; i++) {
     int c, rb, hi;
@@ -49,7 +49,7 @@ __device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, ui
     uint32_t x[R1::E];
     load_global<R1>(x, src, H, col0 + c, rb);
     item_bfly<R1::RB, FWD, LAZY, false>(x, tw, s0 + R1::SL0, s0, hi, PASSB ? col0 + c : 0, q, nfix);
-    store_lds<R1, G::PAD>(x, lds, c, rb);
+    store_lds<R1, G>(x, lds, c, rb);
   }
   __syncthreads();
 #pragma unroll
@@ -57,12 +57,12 @@ __device__ __forceinline__ void pass_body(const uint32_t* src, uint32_t* dst, ui
     int c, rb, hi;
     R2::decode(i * kThreads + threadIdx.x, c, rb, hi);
     uint32_t x[R2::E];
-    load_lds<R2, G::PAD>(x, lds, c, rb);
+    load_lds<R2, G>(x, lds, c, rb);
     // the inverse's strided round of pass A holds global stage 0
     if constexpr (STAGED)
       item_bfly_t<R2::RB, FWD, LAZY, false>(x, TwPassA{ltwa}, R2::SL0, hi, q, nfix);
     else if constexpr (STAGED_B)
-      item_bfly_t<R2::RB, FWD, LAZY, false>(x, TwLds<G::COLS>{ltwa, s0, c}, s0 + R2::SL0, hi, q, nfix);
+      item_bfly_t<R2::RB, FWD, LAZY, false>(x, TwLds<G::COLS, G::RB0>{ltwa, s0, c}, s0 + R2::SL0, hi, q, nfix);
     else
       item_bfly<R2::RB, FWD, LAZY, !FWD && !PASSB>(x, tw, s0 + R2::SL0, s0, hi, PASSB ? col0 + c : 0, q, nfix);
     if constexpr (FINAL) {
@@ -184,14 +184,20 @@ __device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na,
         }
       }
     }
+    // the lazy butterflies take values below 4q: the sum's reduction stays
+    // lazy there (below 3q); the 31-bit primes and the chunked sums of wide
+    // digits need it canonical
     uint32_t x[R1::E];
 #pragma unroll
     for (int j = 0; j < R1::E; j++) {
-      x[j] = redc_2m(acc[j], q, minv);
+      if constexpr (LAZY && ALPHA <= 8)
+        x[j] = redc_lazy(acc[j], q, minv);
+      else
+        x[j] = redc_2m(acc[j], q, minv);
       if constexpr (ALPHA > 8) x[j] = add_mod(part[j], x[j], q);
     }
     item_bfly<R1::RB, true, LAZY, false>(x, tw, R1::SL0, 0, hi, 0, q, nf);
-    store_lds<R1, G::PAD>(x, lds, c, rb);
+    store_lds<R1, G>(x, lds, c, rb);
   }
   __syncthreads();
 #pragma unroll
@@ -199,7 +205,7 @@ __device__ __forceinline__ void modup_a_body(__amdgpu_buffer_rsrc_t src, int na,
     int c, rb, hi;
     R2::decode(i * kModupThreads + threadIdx.x, c, rb, hi);
     uint32_t x[R2::E];
-    load_lds<R2, G::PAD>(x, lds, c, rb);
+    load_lds<R2, G>(x, lds, c, rb);
     item_bfly_t<R2::RB, true, LAZY, false>(x, TwPassA{ltwa}, R2::SL0, hi, q, nf);
     store_global<R2>(x, dst, H, col0 + c, rb);
   }
@@ -303,13 +309,19 @@ __device__ __forceinline__ void modup_a2_body(__amdgpu_buffer_rsrc_t src, int na
     uint32_t x[R1::E];
 #pragma unroll
     for (int j = 0; j < R1::E; j++) {
-      x[j] = redc_2m(a0[j], q0, minv0);
-      y1[i][j] = redc_2m(a1[j], q1, minv1);
+      // lazy reductions (below 3q) feed the lazy butterflies
+      if constexpr (LAZY) {
+        x[j] = redc_lazy(a0[j], q0, minv0);
+        y1[i][j] = redc_lazy(a1[j], q1, minv1);
+      } else {
+        x[j] = redc_2m(a0[j], q0, minv0);
+        y1[i][j] = redc_2m(a1[j], q1, minv1);
+      }
       asm volatile("" : "+v"(x[j]), "+v"(y1[i][j]));  // both sums reduced before the butterflies
     }
     __builtin_amdgcn_sched_barrier(0);
     item_bfly<R1::RB, true, LAZY, false>(x, tw0, R1::SL0, 0, hi, 0, q0, nf);
-    store_lds<R1, G::PAD>(x, lds, c, rb);
+    store_lds<R1, G>(x, lds, c, rb);
     __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
@@ -318,7 +330,7 @@ __device__ __forceinline__ void modup_a2_body(__amdgpu_buffer_rsrc_t src, int na
     int c, rb, hi;
     R2::decode(i * kModupThreads + threadIdx.x, c, rb, hi);
     uint32_t x[R2::E];
-    load_lds<R2, G::PAD>(x, lds, c, rb);
+    load_lds<R2, G>(x, lds, c, rb);
     item_bfly_t<R2::RB, true, LAZY, false>(x, TwPassA{ltw0}, R2::SL0, hi, q0, nf);
     store_global<R2>(x, dst0, H, col0 + c, rb);
   }
@@ -336,7 +348,7 @@ __device__ __forceinline__ void modup_a2_body(__amdgpu_buffer_rsrc_t src, int na
     // the second target's round 1 runs here: its twiddles are not live
     // through the first target's pass
     item_bfly<R1::RB, true, LAZY, false>(y1[i], tw1, R1::SL0, 0, hi, 0, q1, nf);
-    store_lds<R1, G::PAD>(y1[i], lds, c, rb);
+    store_lds<R1, G>(y1[i], lds, c, rb);
   }
   __syncthreads();
 #pragma unroll
@@ -344,7 +356,7 @@ __device__ __forceinline__ void modup_a2_body(__amdgpu_buffer_rsrc_t src, int na
     int c, rb, hi;
     R2::decode(i * kModupThreads + tid, c, rb, hi);
     uint32_t x[R2::E];
-    load_lds<R2, G::PAD>(x, lds, c, rb);
+    load_lds<R2, G>(x, lds, c, rb);
     item_bfly_t<R2::RB, true, LAZY, false>(x, TwPassA{ltw1}, R2::SL0, hi, q1, nf);
     store_global<R2>(x, dst1, H, col0 + c, rb);
   }
@@ -423,11 +435,21 @@ __global__ __launch_bounds__(kModupThreads) __attribute__((amdgpu_waves_per_eu(3
 // ------------------------------------------------------------------ pass B + key inner product
 
 // One wave per workgroup on 1024-element tiles: the pair loop's barriers
-// involve a single wave, and eight workgroups (20 KB of LDS each) share a
-// CU, which is what its 219-245 VGPRs allow.  (8192-element tiles with 512
-// threads: 1121 us per eight-job launch; 4096 / 256: 1075; 2048 / 128: 996;
-// 1024 / 64: 955.)
+// involve a single wave, and eight workgroups share a CU, which is what its
+// 219-245 VGPRs allow.  (8192-element tiles with 512 threads: 1121 us per
+// eight-job launch; 4096 / 256: 1075; 2048 / 128: 996; 1024 / 64: 955.)
 constexpr int kKipThreads = 64;
+
+// The tile, then the staged twiddles (COLS (2^LOGR - 1) pairs), which the
+// second accumulator's tile reuses once the pair loop is done.
+template <int LOGR>
+constexpr int kip_lds_words() {
+  using G = Geo<LOGR, kKipTileLog>;
+  constexpr int tw_words = 2 * G::COLS * ((1 << LOGR) - 1);
+  static_assert(tw_words >= G::LDS_WORDS, "the twiddle area holds a tile");
+  static_assert(G::LDS_WORDS % 4 == 0, "16-byte aligned twiddles");
+  return G::LDS_WORDS + tw_words;
+}
 
 template <int LOGR, bool LAZY>
 __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* De, const uint32_t* evk_e,
@@ -446,7 +468,7 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   // A limb of the only digit (B = 1, e < level) is its own ModUp image in
   // every pair, so it transforms nothing and skips the staging.
   const bool transforms = A.B > 1 || e >= A.level;
-  if (transforms) stage_tw_pass_b<G::COLS, LOGR, kKipThreads>(ltw, tw, s0, col0);
+  if (transforms) stage_tw_pass_b<G::COLS, LOGR, kKipThreads, G::RB0>(ltw, tw, s0, col0);
   // pairs p = (t - 2) B + b.  A pair is "own" when limb e belongs to digit b:
   // its ModUp image is D_t itself (NTT domain, round-2 layout); otherwise the
   // pass-A output X_{t,b,e} is read in round-1 layout.
@@ -509,7 +531,6 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   uint32_t xn[V];
   fetch_x(0, xn);
   __syncthreads();  // twiddles staged
-  int buf = 0;
   for (int p = 0; p < P; p++) {
     const bool own = own_of(p);
     uint32_t x[V];
@@ -521,10 +542,7 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
     fetch_k(p, kk);
     if (p + 1 < P) fetch_x(p + 1, xn);
     if (!own) {
-      // two tile buffers: the next pair's first round may write the other
-      // buffer while slower threads still read this one, so one barrier per
-      // pair suffices
-      uint32_t* tile = lds + buf * G::LDS_WORDS;
+      uint32_t* tile = lds;
 #pragma unroll
       for (int i = 0; i < R1::NI; i++) {
         int c, rb, hi;
@@ -532,8 +550,8 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
         uint32_t y[R1::E];
 #pragma unroll
         for (int j = 0; j < R1::E; j++) y[j] = x[i * R1::E + j];
-        item_bfly_t<R1::RB, true, LAZY, false>(y, TwLds<G::COLS>{ltw, s0, c}, s0 + R1::SL0, hi, q, nf);
-        store_lds<R1, G::PAD>(y, tile, c, rb);
+        item_bfly_t<R1::RB, true, LAZY, false>(y, TwLds<G::COLS, G::RB0>{ltw, s0, c}, s0 + R1::SL0, hi, q, nf);
+        store_lds<R1, G>(y, tile, c, rb);
       }
       __syncthreads();
 #pragma unroll
@@ -541,12 +559,12 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
         int c, rb, hi;
         R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
         uint32_t y[R2::E];
-        load_lds<R2, G::PAD>(y, tile, c, rb);
-        item_bfly_t<R2::RB, true, LAZY, false>(y, TwLds<G::COLS>{ltw, s0, c}, s0 + R2::SL0, hi, q, nf);
+        load_lds<R2, G>(y, tile, c, rb);
+        item_bfly_t<R2::RB, true, LAZY, false>(y, TwLds<G::COLS, G::RB0>{ltw, s0, c}, s0 + R2::SL0, hi, q, nf);
 #pragma unroll
         for (int j = 0; j < R2::E; j++) x[i * R2::E + j] = y[j];
       }
-      buf ^= 1;
+      __syncthreads();  // the tile is read before the next pair writes it
     }
 #pragma unroll
     for (int j = 0; j < V; j += 4) {
@@ -600,13 +618,14 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
       y1[i][j] = o1[j];
     }
   }
-  __syncthreads();  // every thread is done with the pair loop's tiles
+  __syncthreads();  // every thread is done with the tile and the twiddles
+  uint32_t* lds1 = reinterpret_cast<uint32_t*>(ltw);
 #pragma unroll
   for (int i = 0; i < R2::NI; i++) {
     int c, rb, hi;
     R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
-    store_lds<R2, G::PAD>(y0[i], lds, c, rb);
-    store_lds<R2, G::PAD>(y1[i], lds + G::LDS_WORDS, c, rb);
+    store_lds<R2, G>(y0[i], lds, c, rb);
+    store_lds<R2, G>(y1[i], lds1, c, rb);
   }
   __syncthreads();
 #pragma unroll
@@ -614,8 +633,8 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
     int c, rb, hi;
     R1::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
     uint32_t z0[R1::E], z1[R1::E];
-    load_lds<R1, G::PAD>(z0, lds, c, rb);
-    load_lds<R1, G::PAD>(z1, lds + G::LDS_WORDS, c, rb);
+    load_lds<R1, G>(z0, lds, c, rb);
+    load_lds<R1, G>(z1, lds1, c, rb);
     item_bfly<R1::RB, false, LAZY, false>(z0, itw, s0 + R1::SL0, s0, hi, col0 + c, q, nf);
     item_bfly<R1::RB, false, LAZY, false>(z1, itw, s0 + R1::SL0, s0, hi, col0 + c, q, nf);
     store_global<R1>(z0, acc_e, 0, col0 + c, rb);
@@ -628,8 +647,8 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
 template <int LOGR>
 __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const uint32_t* D, const uint32_t* evk,
                                                        uint32_t* acc, KipArgs A, DevTables T) {
-  __shared__ uint32_t lds[2 * Geo<LOGR, kKipTileLog>::LDS_WORDS];
-  __shared__ uint2 ltw[Geo<LOGR, kKipTileLog>::COLS * ((1 << LOGR) - 1)];
+  __shared__ __align__(16) uint32_t lds[kip_lds_words<LOGR>()];
+  uint2* ltw = reinterpret_cast<uint2*>(lds + Geo<LOGR, kKipTileLog>::LDS_WORDS);
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
   const int job = seq % A.n_jobs;
   const int unit = (seq / A.n_jobs) * 8 + xcd;  // (limb e, tile)
@@ -825,8 +844,8 @@ __global__ __launch_bounds__(kModupThreads) __attribute__((amdgpu_waves_per_eu(3
 // ceil(E tiles / 8) 8.
 template <int LOGR>
 __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
-  __shared__ uint32_t lds[2 * Geo<LOGR, kKipTileLog>::LDS_WORDS];
-  __shared__ uint2 ltw[Geo<LOGR, kKipTileLog>::COLS * ((1 << LOGR) - 1)];
+  __shared__ __align__(16) uint32_t lds[kip_lds_words<LOGR>()];
+  uint2* ltw = reinterpret_cast<uint2*>(lds + Geo<LOGR, kKipTileLog>::LDS_WORDS);
   const int j = find_job(jt, nj, S_KIP, blockIdx.x);
   const int local = blockIdx.x - jt[j].blk0[S_KIP];
   const int log_n = G.log_n;

@@ -41,7 +41,8 @@ constexpr int kThreads = 256;
 constexpr int kTileLog = 13;
 
 // TL: log2 of the tile's element count (8192 for the transform passes).
-template <int LOGR, int TL = kTileLog>
+// XP: extra words between blocks of 2^RB1 rows (-1: the default below).
+template <int LOGR, int TL = kTileLog, int XP = -1>
 struct Geo {
   static constexpr int LOGC = TL - LOGR;
   static constexpr int COLS = 1 << LOGC;
@@ -50,10 +51,21 @@ struct Geo {
   // LDS row pitch.  Pass B's strided round gives each column 2^(LOGR-RB0)
   // consecutive lanes (rows lo, lo + 2^(LOGR-RB0), ...), so a 32-lane half
   // touches 32 >> (LOGR-RB0) columns; a pitch of COLS + that count puts
-  // their lanes on distinct banks.  Every other round has 32 consecutive
-  // columns of one row per half, conflict-free at any pitch.
+  // their lanes on distinct banks.
   static constexpr int PAD = COLS + (32 >> (LOGR - RB0));
-  static constexpr int LDS_WORDS = (1 << LOGR) * PAD;
+  // Rows are stored in blocks of 2^RB1 (one consecutive-round item per
+  // column), BP words apart.  With 32 or more columns a half-wave of the
+  // consecutive round reads 32 columns of one row: conflict-free with
+  // BP = 2^RB1 PAD, i.e. plain rows of PAD words.  Narrower tiles (the
+  // key-product and fused tensor kernels) put 32 / COLS blocks in one
+  // half-wave; 2^RB1 PAD is a multiple of 32 there, so every block would hit
+  // the same COLS banks.  A block pitch of COLS times an odd number (mod 32)
+  // spreads them over all 32 banks, and leaves the strided round's lanes
+  // (one block, distinct rows) as they were.
+  static constexpr int XPAD = XP >= 0 ? XP : (COLS >= 32 ? 0 : COLS);
+  static constexpr int BP = (PAD << RB1) + XPAD;
+  static constexpr int LDS_WORDS = BP << RB0;
+  __device__ static int off(int r, int c) { return (r >> RB1) * BP + (r & ((1 << RB1) - 1)) * PAD + c; }
 };
 
 // Item layout of one round.  An item is one column c and 2^RB rows
@@ -210,21 +222,33 @@ __device__ __forceinline__ void stage_tw_pass_a(uint2* ltwa, const uint2* tw) {
   for (int i = threadIdx.x; i < (1 << LOGR); i += NT) ltwa[i] = tw[i];
 }
 
-// The tile's pass-B twiddles staged in LDS: stage s0 + sl, block rr < 2^sl,
-// column c < COLS at COLS (2^sl - 1) + rr COLS + c.
-template <int COLS>
+// The tile's pass-B twiddles staged in LDS: stage s0 + sl at COLS (2^sl - 1),
+// then 2^sl blocks of COLS columns.  The strided round's stages (sl < RB0)
+// hold block rr at position rr; every lane of a column reads the same
+// entry.  In a stage of the consecutive round (u = sl - RB0) the item with
+// row block hi reads blocks rr = hi 2^u + g, g < 2^u; block rr sits at
+// position g 2^RB0 + hi, so that for each g the lanes (row block, column)
+// of a wave read consecutive entries.
+template <int RB0>
+__device__ __forceinline__ int tw_pos(int sl, int rr) {
+  if (sl < RB0) return rr;
+  const int u = sl - RB0;
+  return ((rr & ((1 << u) - 1)) << RB0) + (rr >> u);
+}
+
+template <int COLS, int RB0>
 struct TwLds {
   const uint2* t;
   int s0, c;
   __device__ uint2 operator()(int s, int, int rr) const {
     const int sl = s - s0;
-    return t[COLS * ((1 << sl) - 1) + rr * COLS + c];
+    return t[COLS * ((1 << sl) - 1) + tw_pos<RB0>(sl, rr) * COLS + c];
   }
 };
 
 // Stages the pass-B twiddles of the tile's first NSL stages (sl < NSL) in
 // the TwLds layout; every load is issued before the first LDS store.
-template <int COLS, int NSL, int NT>
+template <int COLS, int NSL, int NT, int RB0>
 __device__ __forceinline__ void stage_tw_pass_b(uint2* ltw, const uint2* tw, int s0, int col0) {
   constexpr int LOGC = __builtin_ctz(COLS);
   constexpr int NTW = COLS * ((1 << NSL) - 1);
@@ -235,9 +259,11 @@ __device__ __forceinline__ void stage_tw_pass_b(uint2* ltw, const uint2* tw, int
     const int i = it * NT + threadIdx.x;
     if (i < NTW) {
       const int c = i & (COLS - 1);
-      const int k = i >> LOGC;  // (2^sl - 1) + rr
+      const int k = i >> LOGC;  // (2^sl - 1) + position
       const int sl = 31 - __clz(k + 1);
-      const int rr = k + 1 - (1 << sl);
+      const int pos = k + 1 - (1 << sl);
+      const int u = sl - RB0;  // the inverse of tw_pos
+      const int rr = u < 0 ? pos : ((pos & ((1 << RB0) - 1)) << u) + (pos >> RB0);
       t[it] = tw[(1 << (s0 + sl)) + (rr << s0) + col0 + c];
     }
   }
@@ -315,16 +341,30 @@ __device__ __forceinline__ void store_global(const uint32_t (&x)[RD::E], uint32_
   }
 }
 
-template <typename RD, int PAD>
-__device__ __forceinline__ void load_lds(uint32_t (&x)[RD::E], const uint32_t* lds, int c, int rbase) {
-#pragma unroll
-  for (int j = 0; j < RD::E; j++) x[j] = lds[RD::row(rbase, j) * PAD + c];
+// Element j of an item sits at base + j step: the strided round walks the
+// blocks of a column (rows lo + j 2^RB1), the consecutive round the rows of
+// one block.
+template <typename RD, typename G>
+__device__ __forceinline__ void lds_item(int c, int rbase, int& base, int& step) {
+  static_assert(RD::NLO_LOG == 0 || RD::NLO_LOG == G::RB1, "rounds of this geometry");
+  base = G::off(rbase, c);
+  step = RD::NLO_LOG == 0 ? G::PAD : G::BP;
 }
 
-template <typename RD, int PAD>
-__device__ __forceinline__ void store_lds(const uint32_t (&x)[RD::E], uint32_t* lds, int c, int rbase) {
+template <typename RD, typename G>
+__device__ __forceinline__ void load_lds(uint32_t (&x)[RD::E], const uint32_t* lds, int c, int rbase) {
+  int base, step;
+  lds_item<RD, G>(c, rbase, base, step);
 #pragma unroll
-  for (int j = 0; j < RD::E; j++) lds[RD::row(rbase, j) * PAD + c] = x[j];
+  for (int j = 0; j < RD::E; j++) x[j] = lds[base + j * step];
+}
+
+template <typename RD, typename G>
+__device__ __forceinline__ void store_lds(const uint32_t (&x)[RD::E], uint32_t* lds, int c, int rbase) {
+  int base, step;
+  lds_item<RD, G>(c, rbase, base, step);
+#pragma unroll
+  for (int j = 0; j < RD::E; j++) lds[base + j * step] = x[j];
 }
 
 }  // namespace

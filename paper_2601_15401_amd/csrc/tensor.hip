@@ -18,15 +18,31 @@ namespace {
 // HBM.  Tiles of 1024 residues from k = 5; 2048 for k = 3, 4 and 4096 for
 // k = 2, so that the k - 1 tiles' round items (64 per 1024 residues at 256
 // rows per block) still cover the 256 threads.
+// Extra words between LDS row blocks of the fused kernel's tiles.  Besides
+// the two rounds, the tile is written by the tensor product itself: a lane
+// stores four consecutive rows of one column, so a half-wave covers 32 / 2^RB1
+// blocks four rows at a time.  Over 32 banks of 4 bytes these pitches leave
+// at most two lanes of a half-wave on one bank in the consecutive round and
+// none in the strided round or the product's stores (one common pitch
+// cannot clear both of the first two everywhere; at 1024 residues and
+// 2^8-row blocks the other candidate, 4, leaves four on one bank in the
+// stores).
+constexpr int tib_xpad(int logr, int tl) {
+  return logr == 8 ? (tl == 10 ? 3 : tl == 11 ? 5 : 1) : logr == 7 ? (tl == 10 ? 5 : 1) : 2;
+}
+
+template <int LOGR, int TL>
+using TibGeo = Geo<LOGR, TL, tib_xpad(LOGR, TL)>;
+
 template <int LOGR, int K>
 constexpr int tib_lds_words() {
-  return (K - 1) * Geo<LOGR, tib_tile_log(K)>::LDS_WORDS;
+  return (K - 1) * TibGeo<LOGR, tib_tile_log(K)>::LDS_WORDS;
 }
 
 template <int LOGR, int K, int TL, bool LAZY>
 __device__ __forceinline__ void tib_rounds(uint32_t* dc, size_t tpoly, uint32_t* lds, const uint2* ltw, int s0,
                                            int col0, uint32_t q) {
-  using G = Geo<LOGR, TL>;
+  using G = TibGeo<LOGR, TL>;
   using R1 = Rnd<LOGR, true, false, kThreads, TL>;  // inverse: consecutive round first
   using R2 = Rnd<LOGR, true, true, kThreads, TL>;
   const uint4 nf{};
@@ -35,9 +51,9 @@ __device__ __forceinline__ void tib_rounds(uint32_t* dc, size_t tpoly, uint32_t*
     int cc, rb, hi;
     R1::decode(it - tt * R1::ITEMS, cc, rb, hi);
     uint32_t x[R1::E];
-    load_lds<R1, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
-    item_bfly_t<R1::RB, false, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, cc}, s0 + R1::SL0, hi, q, nf);
-    store_lds<R1, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
+    load_lds<R1, G>(x, lds + tt * G::LDS_WORDS, cc, rb);
+    item_bfly_t<R1::RB, false, LAZY, false>(x, TwLds<G::COLS, G::RB0>{ltw, s0, cc}, s0 + R1::SL0, hi, q, nf);
+    store_lds<R1, G>(x, lds + tt * G::LDS_WORDS, cc, rb);
   }
   __syncthreads();
   for (int it = threadIdx.x; it < (K - 1) * R2::ITEMS; it += kThreads) {
@@ -45,8 +61,8 @@ __device__ __forceinline__ void tib_rounds(uint32_t* dc, size_t tpoly, uint32_t*
     int cc, rb, hi;
     R2::decode(it - tt * R2::ITEMS, cc, rb, hi);
     uint32_t x[R2::E];
-    load_lds<R2, G::PAD>(x, lds + tt * G::LDS_WORDS, cc, rb);
-    item_bfly_t<R2::RB, false, LAZY, false>(x, TwLds<G::COLS>{ltw, s0, cc}, s0 + R2::SL0, hi, q, nf);
+    load_lds<R2, G>(x, lds + tt * G::LDS_WORDS, cc, rb);
+    item_bfly_t<R2::RB, false, LAZY, false>(x, TwLds<G::COLS, G::RB0>{ltw, s0, cc}, s0 + R2::SL0, hi, q, nf);
     store_global<R2>(x, dc + (size_t)tt * tpoly, 0, col0 + cc, rb);
   }
 }
@@ -59,12 +75,12 @@ __device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], 
                                                const DevTables& T, uint32_t* lds, uint2* ltw) {
   constexpr int TL = tib_tile_log(K);
   constexpr int STEPS = 1 << (TL - 10);  // uint4 groups per thread
-  using G = Geo<LOGR, TL>;
+  using G = TibGeo<LOGR, TL>;
   const size_t N = (size_t)1 << log_n;
   const int s0 = log_n - LOGR;
   const int col0 = tile * G::COLS;
   const uint2* itw = reinterpret_cast<const uint2*>(T.itw) + ((size_t)j << log_n);
-  stage_tw_pass_b<G::COLS, LOGR, kThreads>(ltw, itw, s0, col0);
+  stage_tw_pass_b<G::COLS, LOGR, kThreads, G::RB0>(ltw, itw, s0, col0);
   uint32_t* D = wsj + d_off + (size_t)j * N;
   const size_t tpoly = (size_t)level * N;
   for (int g = 0; g < STEPS; g++) {
@@ -76,14 +92,15 @@ __device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], 
     for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(D + (size_t)t * tpoly)[n] = P[t];
     // residues 4 local .. 4 local + 3: one 2^LOGR-residue block (column c)
     const int e = 4 * local;
-    const int c = e >> LOGR, r = e & ((1 << LOGR) - 1);
+    // (four rows of one row block: 2^RB1 >= 8)
+    const int o = G::off(e & ((1 << LOGR) - 1), e >> LOGR);
 #pragma unroll
     for (int t = 2; t <= K; t++) {
-      uint32_t* tl = lds + (t - 2) * G::LDS_WORDS + c;
-      tl[r * G::PAD] = P[t].x;
-      tl[(r + 1) * G::PAD] = P[t].y;
-      tl[(r + 2) * G::PAD] = P[t].z;
-      tl[(r + 3) * G::PAD] = P[t].w;
+      uint32_t* tl = lds + (t - 2) * G::LDS_WORDS + o;
+      tl[0] = P[t].x;
+      tl[G::PAD] = P[t].y;
+      tl[2 * G::PAD] = P[t].z;
+      tl[3 * G::PAD] = P[t].w;
     }
   }
   __syncthreads();  // d_t tiles and staged twiddles
@@ -102,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_
                                                         uint32_t* ws, long long ws_job, long long d_off,
                                                         long long dc_off, DevTables T) {
   __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
-  __shared__ uint2 ltw[Geo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
+  __shared__ uint2 ltw[TibGeo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
   const size_t job_in = (size_t)blockIdx.z * (size_t)in_job_stride;
   const uint32_t* inp[K];
 #pragma unroll
@@ -118,7 +135,7 @@ template <int LOGR, int K, int TM>
 __global__ __launch_bounds__(kThreads) void k_tensor_ib_jt(const JobDesc* jt, int j0, int nj, int log_n,
                                                            DevTables T) {
   __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
-  __shared__ uint2 ltw[Geo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
+  __shared__ uint2 ltw[TibGeo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
   const int j = j0 + find_job(jt + j0, nj, S_TENSOR, blockIdx.x);
   const int local = blockIdx.x - jt[j].blk0[S_TENSOR];
   const int tiles = 1 << (log_n - tib_tile_log(K));
