@@ -68,14 +68,29 @@ __device__ __forceinline__ uint32_t redc_lazy(uint64_t T, uint32_t m, uint32_t m
   return hi + m - __umulhi(lo * minv, m);
 }
 
-// (hi, lo) += a * b on a 96-bit accumulator: one 32x32+64-bit multiply-add
-// whose carry-out goes to a lane mask, and one add of that carry into hi.
-__device__ __forceinline__ void mac96(uint64_t& lo, uint32_t& hi, uint32_t a, uint32_t b) {
-  uint64_t carry;
-  asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
-      "v_addc_co_u32_e64 %2, %1, 0, %2, %1"
-      : "+v"(lo), "=&s"(carry), "+v"(hi)
-      : "v"(a), "v"(b));
+// Four independent (hi, lo) += a * b on 96-bit accumulators: each is one
+// 32x32+64-bit multiply-add whose carry-out goes to a lane mask and one add
+// of that carry into hi.  The four carries take four lane-mask pairs, so
+// the multiply-adds issue back to back and each carry add comes four
+// instructions after its multiply-add.  (One product per statement gave
+// every statement the same scalar pair, chaining all products of a tile
+// through it with a wait state between statements.)
+__device__ __forceinline__ void mac96x4(uint64_t& l0, uint32_t& h0, uint64_t& l1, uint32_t& h1, uint64_t& l2,
+                                        uint32_t& h2, uint64_t& l3, uint32_t& h3, uint32_t a0, uint32_t b0,
+                                        uint32_t a1, uint32_t b1, uint32_t a2, uint32_t b2, uint32_t a3,
+                                        uint32_t b3) {
+  uint64_t c0, c1, c2, c3;
+  asm("v_mad_u64_u32 %0, %8, %12, %13, %0\n\t"
+      "v_mad_u64_u32 %2, %9, %14, %15, %2\n\t"
+      "v_mad_u64_u32 %4, %10, %16, %17, %4\n\t"
+      "v_mad_u64_u32 %6, %11, %18, %19, %6\n\t"
+      "v_addc_co_u32_e64 %1, %8, 0, %1, %8\n\t"
+      "v_addc_co_u32_e64 %3, %9, 0, %3, %9\n\t"
+      "v_addc_co_u32_e64 %5, %10, 0, %5, %10\n\t"
+      "v_addc_co_u32_e64 %7, %11, 0, %7, %11"
+      : "+v"(l0), "+v"(h0), "+v"(l1), "+v"(h1), "+v"(l2), "+v"(h2), "+v"(l3), "+v"(h3), "=&s"(c0), "=&s"(c1),
+        "=&s"(c2), "=&s"(c3)
+      : "v"(a0), "v"(b0), "v"(a1), "v"(b1), "v"(a2), "v"(b2), "v"(a3), "v"(b3));
 }
 
 // lo32(a b + c d): two chained 32 x 32 + 64-bit multiply-adds, the first

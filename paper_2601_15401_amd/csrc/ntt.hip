@@ -569,14 +569,10 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
 #pragma unroll
     for (int j = 0; j < V; j += 4) {
       const uint4 k0 = kk[j / 2], k1 = kk[j / 2 + 1];
-      mac96(l0[j], h0[j], x[j], k0.x);
-      mac96(l0[j + 1], h0[j + 1], x[j + 1], k0.y);
-      mac96(l0[j + 2], h0[j + 2], x[j + 2], k0.z);
-      mac96(l0[j + 3], h0[j + 3], x[j + 3], k0.w);
-      mac96(l1[j], h1[j], x[j], k1.x);
-      mac96(l1[j + 1], h1[j + 1], x[j + 1], k1.y);
-      mac96(l1[j + 2], h1[j + 2], x[j + 2], k1.z);
-      mac96(l1[j + 3], h1[j + 3], x[j + 3], k1.w);
+      mac96x4(l0[j], h0[j], l0[j + 1], h0[j + 1], l0[j + 2], h0[j + 2], l0[j + 3], h0[j + 3], x[j], k0.x, x[j + 1],
+              k0.y, x[j + 2], k0.z, x[j + 3], k0.w);
+      mac96x4(l1[j], h1[j], l1[j + 1], h1[j + 1], l1[j + 2], h1[j + 2], l1[j + 3], h1[j + 3], x[j], k1.x, x[j + 1],
+              k1.y, x[j + 2], k1.z, x[j + 3], k1.w);
     }
   }
   // sum mod q, then the key's factor R = 2^32 removed by one Montgomery step
