@@ -528,16 +528,13 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
     l0[j] = l1[j] = 0;
     h0[j] = h1[j] = 0;
   }
-  uint32_t xn[V];
-  fetch_x(0, xn);
-  __syncthreads();  // twiddles staged
-  for (int p = 0; p < P; p++) {
+  // One pair: x holds its input (transformed in place), xn receives the
+  // next pair's.  The loop runs two pairs per iteration with the buffers'
+  // roles swapped, so no copy carries the prefetch from one pair to the next.
+  auto pair = [&](int p, uint32_t (&x)[V], uint32_t (&xn)[V]) {
     const bool own = own_of(p);
-    uint32_t x[V];
-#pragma unroll
-    for (int j = 0; j < V; j++) x[j] = xn[j];
     // key words of this pair arrive while it is transformed; the next pair's
-    // input arrives during this whole iteration
+    // input arrives during this whole pair
     uint4 kk[V / 2];
     fetch_k(p, kk);
     if (p + 1 < P) fetch_x(p + 1, xn);
@@ -574,7 +571,16 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
       mac96x4(l1[j], h1[j], l1[j + 1], h1[j + 1], l1[j + 2], h1[j + 2], l1[j + 3], h1[j + 3], x[j], k1.x, x[j + 1],
               k1.y, x[j + 2], k1.z, x[j + 3], k1.w);
     }
+  };
+  uint32_t xa[V], xb[V];
+  fetch_x(0, xa);
+  __syncthreads();  // twiddles staged
+  int p = 0;
+  for (; p + 1 < P; p += 2) {
+    pair(p, xa, xb);
+    pair(p + 1, xb, xa);
   }
+  if (p < P) pair(p, xa, xb);
   // sum mod q, then the key's factor R = 2^32 removed by one Montgomery step
   const uint32_t r32 = red.r32, r32sh = red.r32sh;
   auto finish = [&](uint64_t lo, uint32_t hi) {
