@@ -108,6 +108,18 @@ __device__ __forceinline__ uint32_t mad2_lo(uint32_t a, uint32_t b, uint32_t c, 
   return (uint32_t)p;
 }
 
+// lo32(a b + c d + e) with d and e uniform: as mad2_lo, with e as the first
+// multiply-add's 64-bit addend.
+__device__ __forceinline__ uint32_t mad2_lo_add(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e) {
+  uint64_t p, cy;  // cy: carry-out lane mask, unused
+  const uint64_t e64 = e;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %6\n\t"
+      "v_mad_u64_u32 %0, %1, %4, %5, %0"
+      : "=&v"(p), "=&s"(cy)
+      : "v"(a), "v"(b), "v"(c), "s"(d), "s"(e64));
+  return (uint32_t)p;
+}
+
 // Shoup product in [0, 2m) with negm = 2^32 - m: y w + floor(y w' / 2^32)
 // (2^32 - m) mod 2^32 = y w - floor(y w' / 2^32) m, the value of shoup_lazy
 // in three instructions.

@@ -109,18 +109,24 @@ struct Rnd {
 // so one chain of two multiply-adds gives nt = h q - y w mod 2^32 = -t for
 // the lazy Shoup product t = y w - h q in [0, 2q), h = floor(y w' / 2^32);
 // then x + t and x - t + 2q are a subtraction and one three-operand add.
+// Primes above 2^30 (2q < 2^32 <= 4q) keep values below 2q: the chain adds
+// q as well, v = q - t mod 2^32, and s = min(v, v + q) lies in [0, q] with
+// s = q - t mod q (t < q: s = v; t >= q: v wraps, v + q = 2q - t), so the
+// outputs are a + q - s and a + s for the reduced x = a in [0, q): ten
+// instructions.
 template <bool LAZY>
 __device__ __forceinline__ void ct(uint32_t& x, uint32_t& y, uint2 w, uint32_t q) {
-  const uint32_t nt = mad2_lo(y, w.x, __umulhi(y, w.y), q);
   if constexpr (LAZY) {  // x, y < 4q -> outputs < 4q
+    const uint32_t nt = mad2_lo(y, w.x, __umulhi(y, w.y), q);
     const uint32_t a = min(x, x - 2 * q);
     x = a - nt;
     y = a + nt + 2 * q;
-  } else {  // x, y < 2q -> outputs < 2q
+  } else {  // x < 2q -> outputs < 2q
+    const uint32_t v = mad2_lo_add(y, w.x, __umulhi(y, w.y), q, q);
+    const uint32_t s = min(v, v + q);
     const uint32_t a = red1(x, q);
-    const uint32_t t = red1(0u - nt, q);
-    x = a + t;
-    y = a - t + q;
+    x = a - s + q;
+    y = a + s;
   }
 }
 
