@@ -472,15 +472,27 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   // pairs p = (t - 2) B + b.  A pair is "own" when limb e belongs to digit b:
   // its ModUp image is D_t itself (NTT domain, round-2 layout); otherwise the
   // pass-A output X_{t,b,e} is read in round-1 layout.
+  // A pair's position (t - 2, b) advances by counting, not by dividing
+  // the pair index by B.
+  struct Pos {
+    int t2, b;
+  };
   const int P = (A.k - 1) * A.B;
-  auto own_of = [&](int p) {
-    const int lo = (p % A.B) * A.alpha;
+  auto next = [&](Pos u) {
+    if (++u.b == A.B) {
+      u.b = 0;
+      ++u.t2;
+    }
+    return u;
+  };
+  auto own_of = [&](Pos u) {
+    const int lo = u.b * A.alpha;
     return e >= lo && e < min(lo + A.alpha, A.level);
   };
   // the transform input of one pair
-  auto fetch_x = [&](int p, uint32_t (&xv)[V]) {
-    if (own_of(p)) {
-      const uint32_t* d = De + (size_t)(p / A.B + 2) * A.level * N;
+  auto fetch_x = [&](Pos u, uint32_t (&xv)[V]) {
+    if (own_of(u)) {
+      const uint32_t* d = De + (size_t)(u.t2 + 2) * A.level * N;
 #pragma unroll
       for (int i = 0; i < R2::NI; i++) {
         int c, rb, hi;
@@ -491,7 +503,7 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
         for (int j = 0; j < R2::E; j++) xv[i * R2::E + j] = x[j];
       }
     } else {
-      const uint32_t* src = Xe + (size_t)p * A.E * N;
+      const uint32_t* src = Xe + (size_t)(u.t2 * A.B + u.b) * A.E * N;
 #pragma unroll
       for (int i = 0; i < R1::NI; i++) {
         int c, rb, hi;
@@ -504,9 +516,8 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
     }
   };
   // both key words of every round-2 position of this thread
-  auto fetch_k = [&](int p, uint4 (&kv)[V / 2]) {
-    const int t2 = p / A.B, b = p - t2 * A.B;
-    const uint32_t* k0p = evk_e + (((size_t)t2 * A.dnum + b) * 2) * (size_t)A.key_poly;
+  auto fetch_k = [&](Pos u, uint4 (&kv)[V / 2]) {
+    const uint32_t* k0p = evk_e + (((size_t)u.t2 * A.dnum + u.b) * 2) * (size_t)A.key_poly;
     const uint32_t* k1p = k0p + A.key_poly;
 #pragma unroll
     for (int i = 0; i < R2::NI; i++) {
@@ -531,13 +542,13 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   // One pair: x holds its input (transformed in place), xn receives the
   // next pair's.  The loop runs two pairs per iteration with the buffers'
   // roles swapped, so no copy carries the prefetch from one pair to the next.
-  auto pair = [&](int p, uint32_t (&x)[V], uint32_t (&xn)[V]) {
-    const bool own = own_of(p);
+  auto pair = [&](Pos u, bool more, uint32_t (&x)[V], uint32_t (&xn)[V]) {
+    const bool own = own_of(u);
     // key words of this pair arrive while it is transformed; the next pair's
     // input arrives during this whole pair
     uint4 kk[V / 2];
-    fetch_k(p, kk);
-    if (p + 1 < P) fetch_x(p + 1, xn);
+    fetch_k(u, kk);
+    if (more) fetch_x(next(u), xn);
     if (!own) {
       uint32_t* tile = lds;
 #pragma unroll
@@ -573,14 +584,17 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
     }
   };
   uint32_t xa[V], xb[V];
-  fetch_x(0, xa);
+  Pos u{0, 0};
+  fetch_x(u, xa);
   __syncthreads();  // twiddles staged
   int p = 0;
   for (; p + 1 < P; p += 2) {
-    pair(p, xa, xb);
-    pair(p + 1, xb, xa);
+    pair(u, true, xa, xb);
+    u = next(u);
+    pair(u, p + 2 < P, xb, xa);
+    u = next(u);
   }
-  if (p < P) pair(p, xa, xb);
+  if (p < P) pair(u, false, xa, xb);
   // sum mod q, then the key's factor R = 2^32 removed by one Montgomery step
   const uint32_t r32 = red.r32, r32sh = red.r32sh;
   auto finish = [&](uint64_t lo, uint32_t hi) {
