@@ -112,20 +112,28 @@ __device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], 
     tib_rounds<LOGR, K, TL, false>(dc, tpoly, lds, ltw, s0, col0, q);
 }
 
-// Grid: (N / 2^tib_tile_log(K) tiles, level limbs, jobs); per job ws_job
-// words of workspace.
+// Grid: ceil(level tiles / 8) 8 n_jobs workgroups over (limb, tile) units
+// and jobs; per job ws_job words of workspace.  Block b runs on XCD b mod 8,
+// and the jobs of one unit follow each other there, so all but the first
+// read the unit's staged twiddles from that XCD's L2.
 template <int LOGR, int K, int TM>
 __global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_job_stride, int level, int log_n,
                                                         uint32_t* ws, long long ws_job, long long d_off,
-                                                        long long dc_off, DevTables T) {
+                                                        long long dc_off, int n_jobs, DevTables T) {
   __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
   __shared__ uint2 ltw[TibGeo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
-  const size_t job_in = (size_t)blockIdx.z * (size_t)in_job_stride;
+  const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
+  const int job = seq % n_jobs;
+  const int unit = (seq / n_jobs) * 8 + xcd;
+  const int tiles = 1 << (log_n - tib_tile_log(K));
+  if (unit >= level * tiles) return;  // the last group's padding
+  const int j = unit / tiles, tile = unit - j * tiles;
+  const size_t job_in = (size_t)job * (size_t)in_job_stride;
   const uint32_t* inp[K];
 #pragma unroll
   for (int u = 0; u < K; u++) inp[u] = in.p[u] + job_in;
-  tensor_ib_tile<LOGR, K, TM>(inp, level, log_n, blockIdx.y, blockIdx.x, ws + (size_t)blockIdx.z * (size_t)ws_job,
-                          (size_t)d_off, (size_t)dc_off, T, lds, ltw);
+  tensor_ib_tile<LOGR, K, TM>(inp, level, log_n, j, tile, ws + (size_t)job * (size_t)ws_job, (size_t)d_off,
+                              (size_t)dc_off, T, lds, ltw);
 }
 
 // Job-table form: jobs [j0, j0 + nj) of equal k; blocks per job
@@ -162,11 +170,13 @@ __global__ __launch_bounds__(kThreads) void k_tensor_ib_jt(const JobDesc* jt, in
 
 int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,
                      uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs, hipStream_t s) {
-  dim3 grid((unsigned)(prm->N >> tib_tile_log(k)), (unsigned)level, (unsigned)n_jobs);
+  const long long units = (long long)(prm->N >> tib_tile_log(k)) * level;
+  dim3 grid((unsigned)(((units + 7) / 8) * 8 * n_jobs));
   const DevTables& T = prm->dt;
   const int ln = prm->log_n;
   ProfScope ps(P_TENSOR_IB, s);
-#define MICK_TIB(LR, KK) MICK_TIB_TM(LR, KK, k_tensor_ib, (in, in_job_stride, level, ln, ws, ws_job, d_off, dc_off, T), grid)
+#define MICK_TIB(LR, KK) \
+  MICK_TIB_TM(LR, KK, k_tensor_ib, (in, in_job_stride, level, ln, ws, ws_job, d_off, dc_off, n_jobs, T), grid)
 #define MICK_TIB_K(LR)                                                   \
   switch (k) {                                                           \
     case 2: MICK_TIB(LR, 2); break;                                      \
