@@ -18,6 +18,7 @@ namespace {
 // HBM.  Tiles of 1024 residues from k = 5; 2048 for k = 3, 4 and 4096 for
 // k = 2, so that the k - 1 tiles' round items (64 per 1024 residues at 256
 // rows per block) still cover the 256 threads.
+
 // Extra words between LDS row blocks of the fused kernel's tiles.  Besides
 // the two rounds, the tile is written by the tensor product itself: a lane
 // stores four consecutive rows of one column, so a half-wave covers 32 / 2^RB1
