@@ -477,17 +477,22 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   struct Pos {
     int t2, b;
   };
-  const int P = (A.k - 1) * A.B;
-  auto next = [&](Pos u) {
-    if (++u.b == A.B) {
-      u.b = 0;
-      ++u.t2;
-    }
-    return u;
-  };
   auto own_of = [&](Pos u) {
     const int lo = u.b * A.alpha;
     return e >= lo && e < min(lo + A.alpha, A.level);
+  };
+  // With the own-digit sums precomputed, a q limb's pairs of its own digit
+  // (one per t) are skipped: the accumulators start from those sums.
+  const bool sums = A.own_sums && e < A.level;
+  const int P = (A.k - 1) * A.B - (sums ? A.k - 1 : 0);
+  auto next = [&](Pos u) {
+    do {
+      if (++u.b == A.B) {
+        u.b = 0;
+        ++u.t2;
+      }
+    } while (sums && u.t2 < A.k - 1 && own_of(u));
+    return u;
   };
   // the transform input of one pair
   auto fetch_x = [&](Pos u, uint32_t (&xv)[V]) {
@@ -539,6 +544,21 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
     l0[j] = l1[j] = 0;
     h0[j] = h1[j] = 0;
   }
+  if (sums) {  // the own-digit sums (residues mod q), in round-2 layout
+#pragma unroll
+    for (int i = 0; i < R2::NI; i++) {
+      int c, rb, hi;
+      R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
+      uint32_t o0[R2::E], o1[R2::E];
+      load_global<R2>(o0, De + (size_t)2 * A.level * N, 0, col0 + c, rb);
+      load_global<R2>(o1, De + (size_t)3 * A.level * N, 0, col0 + c, rb);
+#pragma unroll
+      for (int j = 0; j < R2::E; j++) {
+        l0[i * R2::E + j] = o0[j];
+        l1[i * R2::E + j] = o1[j];
+      }
+    }
+  }
   // One pair: x holds its input (transformed in place), xn receives the
   // next pair's.  The loop runs two pairs per iteration with the buffers'
   // roles swapped, so no copy carries the prefetch from one pair to the next.
@@ -585,7 +605,8 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   };
   uint32_t xa[V], xb[V];
   Pos u{0, 0};
-  fetch_x(u, xa);
+  if (sums && own_of(u)) u = next(u);
+  if (P > 0) fetch_x(u, xa);
   __syncthreads();  // twiddles staged
   int p = 0;
   for (; p + 1 < P; p += 2) {
@@ -878,6 +899,7 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int
   A.n_jobs = 1;
   A.tiles = 1 << (log_n - kKipTileLog);
   A.key_poly = (long long)(G.L + G.K) << log_n;
+  A.own_sums = own_sums_on(k);  // the table's tensor launches always form them
   const int unit = (local >> 3) * 8 + (local & 7);
   if (unit >= A.E * A.tiles) return;
   const int e = unit / A.tiles;

@@ -70,10 +70,17 @@ __device__ __forceinline__ void tib_rounds(uint32_t* dc, size_t tpoly, uint32_t*
 
 // One tile of limb j: inp the k inputs, wsj the job's workspace with D at
 // d_off ([k+1][level][N]) and the pass-B outputs at dc_off ([k-1][level][N]).
+// With own.evk set (k >= 3), D receives d_0, d_1 and, in slots 2 and 3, the
+// sums over t = 2..k of d_t times the key of s^t for limb j's own digit b
+// (both key polynomials), instead of d_2..d_k: in the key inner product a
+// limb's own-digit pairs need no transform (the ModUp image of d_t on its own
+// digit is d_t itself), so they are summed here, where d_t is at hand,
+// rather than read back from HBM by the key-product kernel.
 template <int LOGR, int K, int TM>
 __device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], int level, int log_n, int j,
                                                int tile, uint32_t* wsj, size_t d_off, size_t dc_off,
-                                               const DevTables& T, uint32_t* lds, uint2* ltw) {
+                                               const DevTables& T, const OwnKeys& own, uint32_t* lds,
+                                               uint2* ltw) {
   constexpr int TL = tib_tile_log(K);
   constexpr int STEPS = 1 << (TL - 10);  // uint4 groups per thread
   using G = TibGeo<LOGR, TL>;
@@ -89,8 +96,39 @@ __device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], 
     const size_t n = (size_t)tile * (STEPS * kThreads) + local;
     uint4 P[K + 1];
     tensor4_by<K, TM>(inp, level, log_n, j, n, T, P);
+    bool sums = false;
+    if constexpr (K >= 3) sums = own.evk != nullptr;
+    if (sums) {
+      // at most 11 products of canonical residues below 2^30 per sum: exact
+      // in 64 bits, reduced once
+      const int b = j / own.alpha;
+      uint64_t s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(D + (size_t)t * tpoly)[n] = P[t];
+      for (int t = 2; t <= K; t++) {
+        const uint32_t* kp =
+            own.evk + (((size_t)(t - 2) * own.dnum + b) * 2) * (size_t)own.key_poly + (size_t)j * N;
+        const uint4 a0 = reinterpret_cast<const uint4*>(kp)[n];
+        const uint4 a1 = reinterpret_cast<const uint4*>(kp + own.key_poly)[n];
+        s0[0] += (uint64_t)P[t].x * a0.x;
+        s0[1] += (uint64_t)P[t].y * a0.y;
+        s0[2] += (uint64_t)P[t].z * a0.z;
+        s0[3] += (uint64_t)P[t].w * a0.w;
+        s1[0] += (uint64_t)P[t].x * a1.x;
+        s1[1] += (uint64_t)P[t].y * a1.y;
+        s1[2] += (uint64_t)P[t].z * a1.z;
+        s1[3] += (uint64_t)P[t].w * a1.w;
+      }
+      const Red64& rd = T.red[j];
+      const uint4 o0{reduce64(s0[0], rd), reduce64(s0[1], rd), reduce64(s0[2], rd), reduce64(s0[3], rd)};
+      const uint4 o1{reduce64(s1[0], rd), reduce64(s1[1], rd), reduce64(s1[2], rd), reduce64(s1[3], rd)};
+      reinterpret_cast<uint4*>(D)[n] = P[0];
+      reinterpret_cast<uint4*>(D + tpoly)[n] = P[1];
+      reinterpret_cast<uint4*>(D + 2 * tpoly)[n] = o0;
+      reinterpret_cast<uint4*>(D + 3 * tpoly)[n] = o1;
+    } else {
+#pragma unroll
+      for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(D + (size_t)t * tpoly)[n] = P[t];
+    }
     // residues 4 local .. 4 local + 3: one 2^LOGR-residue block (column c)
     const int e = 4 * local;
     // (four rows of one row block: 2^RB1 >= 8)
@@ -120,7 +158,7 @@ __device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], 
 template <int LOGR, int K, int TM>
 __global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_job_stride, int level, int log_n,
                                                         uint32_t* ws, long long ws_job, long long d_off,
-                                                        long long dc_off, int n_jobs, DevTables T) {
+                                                        long long dc_off, int n_jobs, OwnKeys own, DevTables T) {
   __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
   __shared__ uint2 ltw[TibGeo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
@@ -134,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_
 #pragma unroll
   for (int u = 0; u < K; u++) inp[u] = in.p[u] + job_in;
   tensor_ib_tile<LOGR, K, TM>(inp, level, log_n, j, tile, ws + (size_t)job * (size_t)ws_job, (size_t)d_off,
-                              (size_t)dc_off, T, lds, ltw);
+                              (size_t)dc_off, T, own, lds, ltw);
 }
 
 // Job-table form: jobs [j0, j0 + nj) of equal k; blocks per job
@@ -142,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_
 // in the job's workspace (WsLayout).
 template <int LOGR, int K, int TM>
 __global__ __launch_bounds__(kThreads) void k_tensor_ib_jt(const JobDesc* jt, int j0, int nj, int log_n,
-                                                           DevTables T) {
+                                                           OwnKeys own, DevTables T) {
   __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
   __shared__ uint2 ltw[TibGeo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
   const int j = j0 + find_job(jt + j0, nj, S_TENSOR, blockIdx.x);
@@ -155,7 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_tensor_ib_jt(const JobDesc* jt, in
   for (int u = 0; u < K; u++) inp[u] = jt[j].in[u];
   const size_t N = (size_t)1 << log_n;
   tensor_ib_tile<LOGR, K, TM>(inp, level, log_n, local / tiles, local % tiles, jt[j].ws, 0,
-                          (size_t)(K + 1) * level * N, T, lds, ltw);
+                              (size_t)(K + 1) * level * N, T, own, lds, ltw);
 }
 
 }  // namespace
@@ -170,14 +208,15 @@ __global__ __launch_bounds__(kThreads) void k_tensor_ib_jt(const JobDesc* jt, in
   }
 
 int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,
-                     uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs, hipStream_t s) {
+                     uint32_t* ws, long long ws_job, long long d_off, long long dc_off, int n_jobs,
+                     const OwnKeys& own, hipStream_t s) {
   const long long units = (long long)(prm->N >> tib_tile_log(k)) * level;
   dim3 grid((unsigned)(((units + 7) / 8) * 8 * n_jobs));
   const DevTables& T = prm->dt;
   const int ln = prm->log_n;
   ProfScope ps(P_TENSOR_IB, s);
 #define MICK_TIB(LR, KK) \
-  MICK_TIB_TM(LR, KK, k_tensor_ib, (in, in_job_stride, level, ln, ws, ws_job, d_off, dc_off, n_jobs, T), grid)
+  MICK_TIB_TM(LR, KK, k_tensor_ib, (in, in_job_stride, level, ln, ws, ws_job, d_off, dc_off, n_jobs, own, T), grid)
 #define MICK_TIB_K(LR)                                                   \
   switch (k) {                                                           \
     case 2: MICK_TIB(LR, 2); break;                                      \
@@ -205,12 +244,12 @@ int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_
 }
 
 int launch_tensor_ib_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks,
-                        hipStream_t s) {
+                        const OwnKeys& own, hipStream_t s) {
   if (blocks <= 0) return MICK_OK;
   const DevTables& T = prm->dt;
   const int ln = prm->log_n;
   ProfScope ps(P_TENSOR_IB, s);
-#define MICK_TIB(LR, KK) MICK_TIB_TM(LR, KK, k_tensor_ib_jt, (jt, j0, nj, ln, T), blocks)
+#define MICK_TIB(LR, KK) MICK_TIB_TM(LR, KK, k_tensor_ib_jt, (jt, j0, nj, ln, own, T), blocks)
 #define MICK_TIB_K(LR)                                                   \
   switch (k) {                                                           \
     case 2: MICK_TIB(LR, 2); break;                                      \
