@@ -353,10 +353,10 @@ Layout mul_layout(const mick_params* prm, int k, int level) {
   return l;
 }
 
-// The keys for the fused tensor kernel's own-digit sums (none below k = 3).
-OwnKeys own_keys(const mick_params* prm, const mick_keys* keys, int k) {
+// The keys for the fused tensor kernel's own-digit sums.
+OwnKeys own_keys(const mick_params* prm, const mick_keys* keys) {
   OwnKeys o{};
-  o.evk = own_sums_on(k) ? keys->d_evk : nullptr;
+  o.evk = keys->d_evk;
   o.dnum = prm->dnum;
   o.alpha = prm->alpha;
   o.key_poly = (long long)(prm->L + prm->K) * prm->N;
@@ -374,8 +374,8 @@ int check_mul(const mick_params* prm, const mick_keys* keys, int k, int level) {
 
 // Relinearisation and rescale of jobs whose tensor products are already in
 // the workspace (D at the start of each job block).  d_pass_b: the first pass
-// of d_2..d_k's INTT has run too (k_tensor_ib), its output in dcoef, and from
-// k = 3 D holds the own-digit key sums in place of d_2..d_k.
+// of d_2..d_k's INTT has run too (k_tensor_ib), its output in dcoef, and D
+// holds the own-digit key sums (with d_0, d_1) in place of d_0..d_k.
 int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int level, int mu, uint32_t* ws,
                      size_t job_stride, int n_jobs, uint32_t* out, size_t out_job, hipStream_t s,
                      bool d_pass_b = false) {
@@ -418,7 +418,7 @@ int relin_rescale_ws(const mick_params* prm, const mick_keys* keys, int k, int l
   ka.n_jobs = n_jobs;
   ka.key_poly = (long long)(L + K) * N;
   ka.d_job = ka.x_job = ka.acc_job = (long long)job_stride;
-  ka.own_sums = d_pass_b && own_sums_on(k);  // the fused tensor kernel formed them
+  ka.own_sums = d_pass_b;  // the fused tensor kernel formed them
   MICK_TRY(launch_kip_b(prm, ws + lay.X, ws + lay.D, keys->d_evk, ws + lay.acc, ka, s));
   // relocated ModDown: INTT of every accumulator limb (its first pass ran in
   // the key-product kernel)
@@ -1090,7 +1090,7 @@ int mick_mul_relin_rescale(const mick_params* prm, const mick_keys* keys, const 
   const bool fuse = tensor_takes_pass_b(k);
   if (fuse)
     MICK_TRY(launch_tensor_ib(prm, in, 0, k, level, w, 0, (long long)lay.D, (long long)lay.dcoef, 1,
-                              own_keys(prm, keys, k), s));
+                              own_keys(prm, keys), s));
   else
     MICK_TRY(launch_tensor(prm, in, 0, k, level, w + lay.D, 0, 1, s));
   return relin_rescale_ws(prm, keys, k, level, k - 1, w, lay.total, 1, ct_out_dev, 0, s, fuse);
@@ -1130,7 +1130,7 @@ int mick_mul_relin_rescale_batch(const mick_params* prm, const mick_keys* keys, 
   const bool fuse = tensor_takes_pass_b(k);
   if (fuse)
     MICK_TRY(launch_tensor_ib(prm, in, (long long)(k * ct_elems), k, level, w, (long long)lay.total,
-                              (long long)lay.D, (long long)lay.dcoef, n_jobs, own_keys(prm, keys, k), s));
+                              (long long)lay.D, (long long)lay.dcoef, n_jobs, own_keys(prm, keys), s));
   else
     MICK_TRY(launch_tensor(prm, in, (long long)(k * ct_elems), k, level, w + lay.D, (long long)lay.total, n_jobs, s));
   const size_t out_job = 2 * (size_t)(level - k + 1) * N;
@@ -1417,7 +1417,7 @@ int mick_plan_execute(const mick_plan* plan, void* stream) {
   for (size_t i = 0; i < plan->runs.size(); i++) {
     const auto& r = plan->runs[i];
     const int j1 = i + 1 < plan->runs.size() ? plan->runs[i + 1].j0 : n;
-    MICK_TRY(launch_tensor_ib_jt(prm, djt, r.j0, j1 - r.j0, r.k, r.tensor_blocks, own_keys(prm, plan->keys, r.k),
+    MICK_TRY(launch_tensor_ib_jt(prm, djt, r.j0, j1 - r.j0, r.k, r.tensor_blocks, own_keys(prm, plan->keys),
                                  s));
   }
   MICK_TRY(launch_ntt_jt(prm, djt, n, S_INTT_D, plan->blocks[S_INTT_D], G, s));

@@ -550,8 +550,8 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
       int c, rb, hi;
       R2::decode(i * kKipThreads + threadIdx.x, c, rb, hi);
       uint32_t o0[R2::E], o1[R2::E];
-      load_global<R2>(o0, De + (size_t)2 * A.level * N, 0, col0 + c, rb);
-      load_global<R2>(o1, De + (size_t)3 * A.level * N, 0, col0 + c, rb);
+      load_global<R2>(o0, De, 0, col0 + c, rb);
+      load_global<R2>(o1, De + (size_t)A.level * N, 0, col0 + c, rb);
 #pragma unroll
       for (int j = 0; j < R2::E; j++) {
         l0[i * R2::E + j] = o0[j];
@@ -637,7 +637,7 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
       o0[j] = finish(l0[i * R2::E + j], h0[i * R2::E + j]);
       o1[j] = finish(l1[i * R2::E + j], h1[i * R2::E + j]);
     }
-    if (e < A.level) {  // relocated ModDown input D_l + P^-1 C~ on the q rows
+    if (e < A.level && !sums) {  // relocated ModDown input D_l + P^-1 C~ on the q rows
       uint32_t d0[R2::E], d1[R2::E];
       load_global<R2>(d0, De, 0, col0 + c, rb);
       load_global<R2>(d1, De + (size_t)A.level * N, 0, col0 + c, rb);
@@ -899,7 +899,7 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int
   A.n_jobs = 1;
   A.tiles = 1 << (log_n - kKipTileLog);
   A.key_poly = (long long)(G.L + G.K) << log_n;
-  A.own_sums = own_sums_on(k);  // the table's tensor launches always form them
+  A.own_sums = 1;  // the table's tensor launches always form them
   const int unit = (local >> 3) * 8 + (local & 7);
   if (unit >= A.E * A.tiles) return;
   const int e = unit / A.tiles;

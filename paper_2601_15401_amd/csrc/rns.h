@@ -244,20 +244,18 @@ struct KipArgs {
   long long key_poly;  // elements per key polynomial ((L+K) N)
   long long d_job, x_job, acc_job;
   // 1: the tensor kernel has summed each q limb's own-digit key products
-  // (OwnKeys) into D's slots 2 and 3; those pairs are skipped here
+  // and d_0, d_1 (OwnKeys) into D's slots 0 and 1; those pairs are skipped
+  // here and D is not added at the end
   int own_sums;
 };
 
 // The evaluation keys as the fused tensor kernel reads them for the own
-// digit of each q limb (evk == nullptr: d_2..d_k are written instead).
+// digit of each q limb (evk == nullptr: d_0..d_k are written instead).
 struct OwnKeys {
   const uint32_t* evk;
   int dnum, alpha;
   long long key_poly;  // elements per key polynomial ((L+K) N)
 };
-// The fused tensor kernel forms the own-digit sums from k = 3 (D then has a
-// slot 3 for the second one).
-__host__ __device__ constexpr bool own_sums_on(int k) { return k >= 3; }
 
 struct MdArgs {
   const uint32_t* md;     // [K][2] phat_i^-1 (+Shoup), then [K][L] p_i^-1 mod q_j
@@ -292,8 +290,8 @@ __host__ __device__ constexpr int tib_tile_log(int k) { return k >= 5 ? 10 : (k 
 
 // Job-table form: jobs [j0, j0 + nj) of equal k, blocks as job_blocks counts
 // them; every job of a table takes it (the table's INTT of d_2..d_k then
-// runs its pass A only).  With own.evk set (and own_sums_on(k)) both forms
-// write the own-digit sums into D's slots 2 and 3 in place of d_2..d_k.
+// runs its pass A only).  With own.evk set both forms write the own-digit
+// sums (with d_0, d_1 folded in) into D's slots 0 and 1 in place of d_0..d_k.
 int launch_tensor_ib_jt(const mick_params* prm, const JobDesc* jt, int j0, int nj, int k, int blocks,
                         const OwnKeys& own, hipStream_t s);
 int launch_tensor_ib(const mick_params* prm, const CtPtrs& in, long long in_job_stride, int k, int level,

@@ -10,8 +10,8 @@ namespace {
 // ------------------------------------------------------------------ tensor product + pass B of d_2..d_k's INTT
 
 // One tile of one limb of every d_t: the tensor product (four residues per
-// thread and step, tensor4), all k + 1 limbs written as by k_tensor (d_0,
-// d_1 and the digits' own d_t limbs are read in the NTT domain later), and
+// thread and step, tensor4), written in the NTT domain (all k + 1 limbs as by
+// k_tensor, or given the keys the two own-digit sums of tensor_ib_tile), and
 // d_2..d_k also kept in LDS, where the first pass of their inverse transform
 // (pass B: both of its rounds, twiddles staged once for the k - 1 limbs)
 // runs before its output is written.  The pass then reads nothing back from
@@ -70,12 +70,14 @@ __device__ __forceinline__ void tib_rounds(uint32_t* dc, size_t tpoly, uint32_t*
 
 // One tile of limb j: inp the k inputs, wsj the job's workspace with D at
 // d_off ([k+1][level][N]) and the pass-B outputs at dc_off ([k-1][level][N]).
-// With own.evk set (k >= 3), D receives d_0, d_1 and, in slots 2 and 3, the
-// sums over t = 2..k of d_t times the key of s^t for limb j's own digit b
-// (both key polynomials), instead of d_2..d_k: in the key inner product a
-// limb's own-digit pairs need no transform (the ModUp image of d_t on its own
-// digit is d_t itself), so they are summed here, where d_t is at hand,
-// rather than read back from HBM by the key-product kernel.
+// With own.evk set, D's slots 0 and 1 receive, for each key polynomial c,
+// d_c 2^32 plus the sum over t = 2..k of d_t times the key of s^t for limb
+// j's own digit b, reduced mod q, instead of d_0..d_k.  In the key inner
+// product a limb's own-digit pairs need no transform (the ModUp image of d_t
+// on its own digit is d_t itself), so they are summed here, where d_t is at
+// hand, rather than read back from HBM by the key-product kernel; d_c 2^32
+// becomes d_c after that kernel's final Montgomery step, which is where the
+// relocated ModDown adds it.
 template <int LOGR, int K, int TM>
 __device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], int level, int log_n, int j,
                                                int tile, uint32_t* wsj, size_t d_off, size_t dc_off,
@@ -96,13 +98,14 @@ __device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], 
     const size_t n = (size_t)tile * (STEPS * kThreads) + local;
     uint4 P[K + 1];
     tensor4_by<K, TM>(inp, level, log_n, j, n, T, P);
-    bool sums = false;
-    if constexpr (K >= 3) sums = own.evk != nullptr;
-    if (sums) {
-      // at most 11 products of canonical residues below 2^30 per sum: exact
-      // in 64 bits, reduced once
+    if (own.evk != nullptr) {
+      // d_c 2^32 (below 2^62) and at most 11 products of canonical residues
+      // below 2^30 per sum: exact in 64 bits, reduced once
       const int b = j / own.alpha;
-      uint64_t s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
+      uint64_t s0[4] = {(uint64_t)P[0].x << 32, (uint64_t)P[0].y << 32, (uint64_t)P[0].z << 32,
+                        (uint64_t)P[0].w << 32};
+      uint64_t s1[4] = {(uint64_t)P[1].x << 32, (uint64_t)P[1].y << 32, (uint64_t)P[1].z << 32,
+                        (uint64_t)P[1].w << 32};
 #pragma unroll
       for (int t = 2; t <= K; t++) {
         const uint32_t* kp =
@@ -121,10 +124,8 @@ __device__ __forceinline__ void tensor_ib_tile(const uint32_t* const (&inp)[K], 
       const Red64& rd = T.red[j];
       const uint4 o0{reduce64(s0[0], rd), reduce64(s0[1], rd), reduce64(s0[2], rd), reduce64(s0[3], rd)};
       const uint4 o1{reduce64(s1[0], rd), reduce64(s1[1], rd), reduce64(s1[2], rd), reduce64(s1[3], rd)};
-      reinterpret_cast<uint4*>(D)[n] = P[0];
-      reinterpret_cast<uint4*>(D + tpoly)[n] = P[1];
-      reinterpret_cast<uint4*>(D + 2 * tpoly)[n] = o0;
-      reinterpret_cast<uint4*>(D + 3 * tpoly)[n] = o1;
+      reinterpret_cast<uint4*>(D)[n] = o0;
+      reinterpret_cast<uint4*>(D + tpoly)[n] = o1;
     } else {
 #pragma unroll
       for (int t = 0; t <= K; t++) reinterpret_cast<uint4*>(D + (size_t)t * tpoly)[n] = P[t];
