@@ -1300,10 +1300,13 @@ int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* job
   plan->table = table_dev;
   plan->n_jobs = n_jobs;
   // jobs of equal k are contiguous in the table (the tensor and rescale kernels
-  // are specialised on k)
+  // are specialised on k), and within a run sorted by level, descending (the
+  // tensor launch's job-adjacent order, tensor_block)
   std::vector<int> order(n_jobs);
   for (int i = 0; i < n_jobs; i++) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobs[a].k < jobs[b].k; });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return jobs[a].k != jobs[b].k ? jobs[a].k < jobs[b].k : jobs[a].level > jobs[b].level;
+  });
   std::vector<JobDesc>& jt = plan->host_table;
   jt.assign(n_jobs, JobDesc{});
   int total[kStages] = {0};
@@ -1335,6 +1338,23 @@ int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* job
     run.moddown_blocks = total[S_MODDOWN];
   }
   for (int st = 0; st < kStages; st++) plan->blocks[st] = total[st];
+  // each run's tensor segments (tensor_block): group counts, then the bases
+  // from the run's last job up
+  for (size_t ri = 0; ri < plan->runs.size(); ri++) {
+    const int j0 = plan->runs[ri].j0;
+    const int j1 = ri + 1 < plan->runs.size() ? plan->runs[ri + 1].j0 : n_jobs;
+    for (int r = j0; r < j1; r++) {
+      int nb[kStages];
+      job_blocks(prm, jt[r].k, jt[r].level, nb);
+      jt[r].t_groups = nb[S_TENSOR] / 8;
+    }
+    jt[j1 - 1].t_base = 0;
+    for (int r = j1 - 2; r >= j0; r--) {
+      const int i = r - j0;  // the segment of job i + 1 holds groups [G(i + 2), G(i + 1)), i + 2 jobs each
+      const int g_next = r + 2 < j1 ? jt[r + 2].t_groups : 0;
+      jt[r].t_base = jt[r + 1].t_base + (jt[r + 1].t_groups - g_next) * (i + 2);
+    }
+  }
   if (n_jobs > 0)
     MICK_HIP(hipMemcpyAsync(table_dev, jt.data(), n_jobs * sizeof(JobDesc), hipMemcpyHostToDevice, s), "job table");
   *out = plan.release();

@@ -70,7 +70,35 @@ struct JobDesc {
   uint32_t* ws;               // the job's workspace (WsLayout)
   int k, level;
   int blk0[kStages];          // first block of the job in each stage's launch (multiple of 8)
+  // the tensor launch's job-adjacent order (tensor_block): the job's
+  // (limb, tile) units in groups of 8, and where its segment starts
+  int t_groups, t_base;
 };
+
+// The tensor launch of a run of equal k orders its blocks by unit group g
+// (8 units, one per XCD), then by job: within group g the jobs whose units
+// reach it, each with 8 blocks.  The run's jobs are sorted by level,
+// descending, so those jobs are a prefix 0..c_g - 1 of the run, and c_g
+// steps down at each job's group count: job i's segment holds the groups
+// [t_groups(i + 1), t_groups(i)) with i + 1 jobs each, from block group
+// t_base(i) on (t_base(n - 1) = 0; a segment's end is the previous job's
+// base).  Block b -> (job, unit); unit >= the job's units: padding.
+__device__ __forceinline__ void tensor_block(const JobDesc* jt, int n, int b, int& job, int& unit) {
+  const int xcd = b & 7, seq = b >> 3;
+  int lo = 0, hi = n - 1;  // the first job whose segment starts at or before seq
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (jt[mid].t_base <= seq)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const int i = lo;
+  const int g_lo = i + 1 < n ? jt[i + 1].t_groups : 0;
+  const int off = seq - jt[i].t_base;
+  job = off % (i + 1);
+  unit = (g_lo + off / (i + 1)) * 8 + xcd;
+}
 
 // Index (relative to jt) of the last job whose first block in `stage` is <= b.
 __device__ __forceinline__ int find_job(const JobDesc* jt, int n, int stage, int b) {
