@@ -1301,7 +1301,7 @@ int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* job
   plan->n_jobs = n_jobs;
   // jobs of equal k are contiguous in the table (the tensor and rescale kernels
   // are specialised on k), and within a run sorted by level, descending (the
-  // tensor launch's job-adjacent order, tensor_block)
+  // tensor launch's job-adjacent order, seg_block)
   std::vector<int> order(n_jobs);
   for (int i = 0; i < n_jobs; i++) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -1338,22 +1338,38 @@ int plan_jobs(const mick_params* prm, const mick_keys* keys, const mick_job* job
     run.moddown_blocks = total[S_MODDOWN];
   }
   for (int st = 0; st < kStages; st++) plan->blocks[st] = total[st];
-  // each run's tensor segments (tensor_block): group counts, then the bases
-  // from the run's last job up
+  // job-adjacent block orders (seg_block): the segment bases from the last
+  // rank up
+  auto segments = [&](int order, int r0, int r1) {
+    jt[r1 - 1].seg[order].base = 0;
+    for (int r = r1 - 2; r >= r0; r--) {
+      const int i = r - r0;  // rank i + 1's segment: groups [G(i + 2), G(i + 1)), i + 2 ranks each
+      const int g_next = r + 2 < r1 ? jt[r + 2].seg[order].groups : 0;
+      jt[r].seg[order].base = jt[r + 1].seg[order].base + (jt[r + 1].seg[order].groups - g_next) * (i + 2);
+    }
+  };
+  // [0] each run's tensor launch: the run is already in rank order
   for (size_t ri = 0; ri < plan->runs.size(); ri++) {
     const int j0 = plan->runs[ri].j0;
     const int j1 = ri + 1 < plan->runs.size() ? plan->runs[ri + 1].j0 : n_jobs;
     for (int r = j0; r < j1; r++) {
       int nb[kStages];
       job_blocks(prm, jt[r].k, jt[r].level, nb);
-      jt[r].t_groups = nb[S_TENSOR] / 8;
+      jt[r].seg[0] = {r, nb[S_TENSOR] / 8, 0};
     }
-    jt[j1 - 1].t_base = 0;
-    for (int r = j1 - 2; r >= j0; r--) {
-      const int i = r - j0;  // the segment of job i + 1 holds groups [G(i + 2), G(i + 1)), i + 2 jobs each
-      const int g_next = r + 2 < j1 ? jt[r + 2].t_groups : 0;
-      jt[r].t_base = jt[r + 1].t_base + (jt[r + 1].t_groups - g_next) * (i + 2);
+    segments(0, j0, j1);
+  }
+  // [1] the key-product launch over the table: ranks by level, descending
+  if (n_jobs > 0) {
+    std::vector<int> rank(n_jobs);
+    for (int r = 0; r < n_jobs; r++) rank[r] = r;
+    std::stable_sort(rank.begin(), rank.end(), [&](int a, int b) { return jt[a].level > jt[b].level; });
+    for (int r = 0; r < n_jobs; r++) {
+      int nb[kStages];
+      job_blocks(prm, jt[rank[r]].k, jt[rank[r]].level, nb);
+      jt[r].seg[1] = {rank[r], nb[S_KIP] / 8, 0};
     }
+    segments(1, 0, n_jobs);
   }
   if (n_jobs > 0)
     MICK_HIP(hipMemcpyAsync(table_dev, jt.data(), n_jobs * sizeof(JobDesc), hipMemcpyHostToDevice, s), "job table");

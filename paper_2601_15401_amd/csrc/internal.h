@@ -64,40 +64,48 @@ struct WsLayout {
 // block finds its job by binary search over the jobs' first blocks.
 enum Stage { S_TENSOR, S_INTT_D, S_MODUP, S_KIP, S_INTT_ACC, S_MODDOWN, S_NTT_OUT, kStages };
 
+// One rank of a job-adjacent block order (seg_block): the job at that rank
+// (its index in the table), its groups of 8 units, where its segment starts.
+struct Seg {
+  int job, groups, base;
+};
+
 struct JobDesc {
   const uint32_t* in[kMaxK];  // input ciphertexts [2][level][N]
   uint32_t* out;              // output [2][level-k+1][N]
   uint32_t* ws;               // the job's workspace (WsLayout)
   int k, level;
   int blk0[kStages];          // first block of the job in each stage's launch (multiple of 8)
-  // the tensor launch's job-adjacent order (tensor_block): the job's
-  // (limb, tile) units in groups of 8, and where its segment starts
-  int t_groups, t_base;
+  // job-adjacent block orders (seg_block): [0] the tensor launch of the
+  // job's run of equal k, [1] the key-product launch over the whole table
+  Seg seg[2];
 };
 
-// The tensor launch of a run of equal k orders its blocks by unit group g
-// (8 units, one per XCD), then by job: within group g the jobs whose units
-// reach it, each with 8 blocks.  The run's jobs are sorted by level,
-// descending, so those jobs are a prefix 0..c_g - 1 of the run, and c_g
-// steps down at each job's group count: job i's segment holds the groups
-// [t_groups(i + 1), t_groups(i)) with i + 1 jobs each, from block group
-// t_base(i) on (t_base(n - 1) = 0; a segment's end is the previous job's
-// base).  Block b -> (job, unit); unit >= the job's units: padding.
-__device__ __forceinline__ void tensor_block(const JobDesc* jt, int n, int b, int& job, int& unit) {
+// A job-adjacent block order over n jobs ranked by unit count, descending.
+// Blocks go by unit group g (8 units, one per XCD), then by rank: within
+// group g the ranks whose units reach it, 8 blocks each.  Those ranks are a
+// prefix 0..c_g - 1, and c_g steps down at each rank's group count: rank r's
+// segment holds the groups [groups(r + 1), groups(r)) with r + 1 ranks each,
+// from block group base(r) on (base(n - 1) = 0; a segment's end is the
+// previous rank's base).  Block b -> (rank, unit); unit >= the job's units:
+// padding.  The jobs of one unit then run back to back on one XCD and share
+// what the unit reads (twiddles, key words) in its L2.
+template <int ORDER>
+__device__ __forceinline__ void seg_block(const JobDesc* jt, int n, int b, int& rank, int& unit) {
   const int xcd = b & 7, seq = b >> 3;
-  int lo = 0, hi = n - 1;  // the first job whose segment starts at or before seq
+  int lo = 0, hi = n - 1;  // the first rank whose segment starts at or before seq
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (jt[mid].t_base <= seq)
+    if (jt[mid].seg[ORDER].base <= seq)
       hi = mid;
     else
       lo = mid + 1;
   }
-  const int i = lo;
-  const int g_lo = i + 1 < n ? jt[i + 1].t_groups : 0;
-  const int off = seq - jt[i].t_base;
-  job = off % (i + 1);
-  unit = (g_lo + off / (i + 1)) * 8 + xcd;
+  const int r = lo;
+  const int g_lo = r + 1 < n ? jt[r + 1].seg[ORDER].groups : 0;
+  const int off = seq - jt[r].seg[ORDER].base;
+  rank = off % (r + 1);
+  unit = (g_lo + off / (r + 1)) * 8 + xcd;
 }
 
 // Index (relative to jt) of the last job whose first block in `stage` is <= b.

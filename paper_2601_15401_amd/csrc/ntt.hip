@@ -883,8 +883,12 @@ template <int LOGR>
 __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int nj, GroupConsts G, DevTables T) {
   __shared__ __align__(16) uint32_t lds[kip_lds_words<LOGR>()];
   uint2* ltw = reinterpret_cast<uint2*>(lds + Geo<LOGR, kKipTileLog>::LDS_WORDS);
-  const int j = find_job(jt, nj, S_KIP, blockIdx.x);
-  const int local = blockIdx.x - jt[j].blk0[S_KIP];
+  // units (prime, tile) with the special primes first, so that a job's
+  // units are a prefix and a unit is the same prime for every job: the jobs
+  // of one unit share its key words and twiddles in L2 (seg_block)
+  int rank, local;
+  seg_block<1>(jt, nj, blockIdx.x, rank, local);
+  const int j = jt[rank].seg[1].job;
   const int log_n = G.log_n;
   const int k = jt[j].k, level = jt[j].level;
   KipArgs A{};
@@ -900,10 +904,10 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b_jt(const JobDesc* jt, int
   A.tiles = 1 << (log_n - kKipTileLog);
   A.key_poly = (long long)(G.L + G.K) << log_n;
   A.own_sums = 1;  // the table's tensor launches always form them
-  const int unit = (local >> 3) * 8 + (local & 7);
-  if (unit >= A.E * A.tiles) return;
-  const int e = unit / A.tiles;
-  const int tile = unit - e * A.tiles;
+  if (local >= A.E * A.tiles) return;  // the job's last group's padding
+  const int u = local / A.tiles;  // K special primes, then the q limbs
+  const int tile = local - u * A.tiles;
+  const int e = u < G.K ? level + u : u - G.K;
   const int pe = e < level ? e : G.L + (e - level);
   const uint32_t q = T.mod[pe], minv = T.minv[pe];
   const uint2* tw = reinterpret_cast<const uint2*>(T.tw) + ((size_t)pe << log_n);

@@ -177,18 +177,18 @@ __global__ __launch_bounds__(kThreads) void k_tensor_ib(CtPtrs in, long long in_
 }
 
 // Job-table form: jobs [j0, j0 + nj) of equal k, sorted by level
-// (descending); blocks in the job-adjacent order of tensor_block, so that
-// the jobs of one (limb, tile) run back to back on one XCD and share its
-// twiddles and key words in L2.  D and the pass-B outputs at their places in
+// (descending); blocks in the job-adjacent order of seg_block over the
+// run's (limb, tile) units, so that the jobs of one unit run back to back on
+// one XCD and share its twiddles and key words in L2.  D and the pass-B outputs at their places in
 // the job's workspace (WsLayout).
 template <int LOGR, int K, int TM>
 __global__ __launch_bounds__(kThreads) void k_tensor_ib_jt(const JobDesc* jt, int j0, int nj, int log_n,
                                                            OwnKeys own, DevTables T) {
   __shared__ uint32_t lds[tib_lds_words<LOGR, K>()];
   __shared__ uint2 ltw[TibGeo<LOGR, tib_tile_log(K)>::COLS * ((1 << LOGR) - 1)];
-  int jj, local;
-  tensor_block(jt + j0, nj, blockIdx.x, jj, local);
-  const int j = j0 + jj;
+  int rank, local;
+  seg_block<0>(jt + j0, nj, blockIdx.x, rank, local);
+  const int j = j0 + rank;  // the run is in rank order
   const int tiles = 1 << (log_n - tib_tile_log(K));
   const int level = jt[j].level;
   if (local >= tiles * level) return;  // the job's last group's padding

@@ -1,13 +1,14 @@
-"""The job-table tensor launch's job-adjacent block order, checked on the CPU.
+"""The job-table launches' job-adjacent block orders, checked on the CPU.
 
-Within a run of equal k the jobs are sorted by level, descending; job i has
-G_i groups of 8 (limb, tile) units.  Blocks are ordered by unit group, then
-by job, 8 blocks (one per XCD) per job and group.  Each job carries G_i and
-the block group where its segment starts; a block finds its job by binary
-search.  This module restates the plan's segment bases and the kernel's
-decoding (internal.h tensor_block, api.hip plan_jobs) and checks that the
-blocks cover every (job, unit) of the run exactly once, each unit's blocks
-on one XCD, the jobs of a unit back to back."""
+The jobs of a launch (the tensor launch of a run of equal k; the
+key-product launch over the whole table) are ranked by level, descending;
+rank i has G_i groups of 8 units.  Blocks are ordered by unit group, then by
+rank, 8 blocks (one per XCD) per rank and group.  Each rank carries G_i and
+the block group where its segment starts; a block finds its rank by binary
+search.  This module restates the plan's segment bases and the kernels'
+decoding (internal.h seg_block, api.hip plan_jobs) and checks that the
+blocks cover every (rank, unit) exactly once, each unit's blocks on one
+XCD, the ranks of a unit back to back."""
 
 import os
 import random
@@ -42,17 +43,18 @@ def block(groups, base, b):
 
 def test_source_holds_the_same_steps():
     internal = " ".join(open(os.path.join(CSRC, "internal.h")).read().split())
-    for text in ("const int g_lo = i + 1 < n ? jt[i + 1].t_groups : 0;",
-                 "const int off = seq - jt[i].t_base;",
-                 "job = off % (i + 1);",
-                 "unit = (g_lo + off / (i + 1)) * 8 + xcd;",
-                 "if (jt[mid].t_base <= seq) hi = mid; else lo = mid + 1;"):
+    for text in ("const int g_lo = r + 1 < n ? jt[r + 1].seg[ORDER].groups : 0;",
+                 "const int off = seq - jt[r].seg[ORDER].base;",
+                 "rank = off % (r + 1);",
+                 "unit = (g_lo + off / (r + 1)) * 8 + xcd;",
+                 "if (jt[mid].seg[ORDER].base <= seq) hi = mid; else lo = mid + 1;"):
         assert text in internal, text
     api = " ".join(open(os.path.join(CSRC, "api.hip")).read().split())
-    for text in ("jt[r].t_groups = nb[S_TENSOR] / 8;",
-                 "const int g_next = r + 2 < j1 ? jt[r + 2].t_groups : 0;",
-                 "jt[r].t_base = jt[r + 1].t_base + (jt[r + 1].t_groups - g_next) * (i + 2);",
-                 "jobs[a].k != jobs[b].k ? jobs[a].k < jobs[b].k : jobs[a].level > jobs[b].level;"):
+    for text in ("jt[r1 - 1].seg[order].base = 0;",
+                 "const int g_next = r + 2 < r1 ? jt[r + 2].seg[order].groups : 0;",
+                 "jt[r].seg[order].base = jt[r + 1].seg[order].base + (jt[r + 1].seg[order].groups - g_next) * (i + 2);",
+                 "jobs[a].k != jobs[b].k ? jobs[a].k < jobs[b].k : jobs[a].level > jobs[b].level;",
+                 "return jt[a].level > jt[b].level;"):
         assert text in api, text
 
 
