@@ -680,7 +680,10 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
 }
 
 // Workgroup order: the jobs of one (limb, tile) run back to back on one XCD,
-// so the key tiles they share are read from L2.
+// so the key tiles they share are read from L2.  The special primes come
+// first: a q limb skips its own digit's pairs when the tensor kernel has
+// summed them, so the longest units are dispatched before the shorter ones
+// and the last, partly filled round is made of the shorter ones.
 template <int LOGR>
 __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const uint32_t* D, const uint32_t* evk,
                                                        uint32_t* acc, KipArgs A, DevTables T) {
@@ -688,10 +691,11 @@ __global__ __launch_bounds__(kKipThreads) void k_kip_b(const uint32_t* X, const 
   uint2* ltw = reinterpret_cast<uint2*>(lds + Geo<LOGR, kKipTileLog>::LDS_WORDS);
   const int xcd = blockIdx.x & 7, seq = blockIdx.x >> 3;
   const int job = seq % A.n_jobs;
-  const int unit = (seq / A.n_jobs) * 8 + xcd;  // (limb e, tile)
+  const int unit = (seq / A.n_jobs) * 8 + xcd;  // (prime, tile)
   if (unit >= A.E * A.tiles) return;
-  const int e = unit / A.tiles;
-  const int tile = unit - e * A.tiles;
+  const int u = unit / A.tiles, ks = A.E - A.level;  // K special primes, then the q limbs
+  const int tile = unit - u * A.tiles;
+  const int e = u < ks ? A.level + u : u - ks;
   const int pe = e < A.level ? e : A.L + (e - A.level);
   const uint32_t q = T.mod[pe], minv = T.minv[pe];
   const uint2* tw = reinterpret_cast<const uint2*>(T.tw) + ((size_t)pe << A.log_n);
