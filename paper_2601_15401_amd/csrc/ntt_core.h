@@ -42,7 +42,8 @@ constexpr int kTileLog = 13;
 
 // TL: log2 of the tile's element count (8192 for the transform passes).
 // XP: extra words between blocks of 2^RB1 rows (-1: the default below).
-template <int LOGR, int TL = kTileLog, int XP = -1>
+// PD: row pitch (-1: the padded pitch below).
+template <int LOGR, int TL = kTileLog, int XP = -1, int PD = -1>
 struct Geo {
   static constexpr int LOGC = TL - LOGR;
   static constexpr int COLS = 1 << LOGC;
@@ -52,7 +53,7 @@ struct Geo {
   // consecutive lanes (rows lo, lo + 2^(LOGR-RB0), ...), so a 32-lane half
   // touches 32 >> (LOGR-RB0) columns; a pitch of COLS + that count puts
   // their lanes on distinct banks.
-  static constexpr int PAD = COLS + (32 >> (LOGR - RB0));
+  static constexpr int PAD = PD >= 0 ? PD : COLS + (32 >> (LOGR - RB0));
   // Rows are stored in blocks of 2^RB1 (one consecutive-round item per
   // column), BP words apart.  With 32 or more columns a half-wave of the
   // consecutive round reads 32 columns of one row: conflict-free with

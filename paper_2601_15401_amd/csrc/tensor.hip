@@ -19,21 +19,26 @@ namespace {
 // k = 2, so that the k - 1 tiles' round items (64 per 1024 residues at 256
 // rows per block) still cover the 256 threads.
 
-// Extra words between LDS row blocks of the fused kernel's tiles.  Besides
-// the two rounds, the tile is written by the tensor product itself: a lane
-// stores four consecutive rows of one column, so a half-wave covers 32 / 2^RB1
-// blocks four rows at a time.  Over 32 banks of 4 bytes these pitches leave
-// at most two lanes of a half-wave on one bank in the consecutive round and
-// none in the strided round or the product's stores (one common pitch
-// cannot clear both of the first two everywhere; at 1024 residues and
-// 2^8-row blocks the other candidate, 4, leaves four on one bank in the
-// stores).
+// LDS rows and row blocks of the fused kernel's tiles.  Besides the two
+// rounds, the tile is written by the tensor product itself: a lane stores
+// four consecutive rows of one column, so a half-wave covers 32 / 2^RB1
+// blocks four rows at a time.  Over 32 banks of 4 bytes:
+//  * 2048 and 4096 residues (k = 2..4, at most three tiles): padded rows and
+//    these block pitches leave at most two lanes of a half-wave on one bank
+//    in the consecutive round and none in the strided round or the stores;
+//  * 1024 residues (k >= 5, four to eleven tiles) in blocks of 2^7 or 2^8
+//    rows: rows of COLS words, no padding, so that a tile takes 1024 + 16
+//    XPAD words instead of about 1.5 times that and more workgroups fit a
+//    CU's LDS; these pitches leave at most two lanes on one bank in each of
+//    the three access patterns (with 2^6-row blocks unpadded rows would put
+//    four lanes on one bank in the strided round, so those keep the padding).
+constexpr int tib_pad(int logr, int tl) { return tl == 10 && logr >= 7 ? 1 << (tl - logr) : -1; }
 constexpr int tib_xpad(int logr, int tl) {
-  return logr == 8 ? (tl == 10 ? 3 : tl == 11 ? 5 : 1) : logr == 7 ? (tl == 10 ? 5 : 1) : 2;
+  return logr == 8 ? (tl == 10 ? 2 : tl == 11 ? 5 : 1) : logr == 7 ? (tl == 10 ? 5 : 1) : 2;
 }
 
 template <int LOGR, int TL>
-using TibGeo = Geo<LOGR, TL, tib_xpad(LOGR, TL)>;
+using TibGeo = Geo<LOGR, TL, tib_xpad(LOGR, TL), tib_pad(LOGR, TL)>;
 
 template <int LOGR, int K>
 constexpr int tib_lds_words() {

@@ -2,14 +2,14 @@
 
 A tile of 2^LOGR rows by COLS columns sits in LDS as blocks of 2^RB1 rows
 (one consecutive-round item per column): element (r, c) at
-(r >> RB1) BP + (r mod 2^RB1) PAD + c, with PAD = COLS + 32 >> RB1 and
-BP = 2^RB1 PAD + XPAD.  This module restates that rule, checks that it is
+(r >> RB1) BP + (r mod 2^RB1) PAD + c, with PAD = COLS + 32 >> RB1 (or a
+given pitch) and BP = 2^RB1 PAD + XPAD.  This module restates that rule, checks that it is
 a one-to-one map into the tile's words, and runs every round's lane map
 through a bank model (32 banks of 4 bytes; a 32-bit access is served a
 half-wave of 32 lanes at a time, and lanes of a half-wave on one bank
 serialise unless they read the same word).  The extra block pitches
-(XPAD) are read from the kernel sources so that a change there must pass
-the same checks."""
+(XPAD) and the fused tensor kernel's row pitch are read from the kernel
+sources so that a change there must pass the same checks."""
 
 import os
 import re
@@ -19,11 +19,11 @@ import pytest
 CSRC = os.path.join(os.path.dirname(__file__), "..", "paper_2601_15401_amd", "csrc")
 
 
-def geo(logr, tl, xp):
+def geo(logr, tl, xp, pd=-1):
     cols = 1 << (tl - logr)
     rb0 = 3 if logr == 6 else 4
     rb1 = logr - rb0
-    pad = cols + (32 >> rb1)
+    pad = pd if pd >= 0 else cols + (32 >> rb1)
     xpad = xp if xp >= 0 else (0 if cols >= 32 else cols)
     bp = (pad << rb1) + xpad
     return dict(cols=cols, logc=tl - logr, rb0=rb0, rb1=rb1, pad=pad, bp=bp, words=bp << rb0)
@@ -92,6 +92,20 @@ def product_stores(g, logr, tl, nt):
     return res
 
 
+def tensor_pad(logr, tl):
+    """tib_pad(logr, tl) as written in tensor.hip: rows of COLS words (no
+    padding) for 1024-residue tiles in blocks of 2^7 or 2^8 rows, the padded
+    pitch otherwise."""
+    src = " ".join(open(os.path.join(CSRC, "tensor.hip")).read().split())
+    assert "constexpr int tib_pad(int logr, int tl) { return tl == 10 && logr >= 7 ? 1 << (tl - logr) : -1; }" in src
+    assert "using TibGeo = Geo<LOGR, TL, tib_xpad(LOGR, TL), tib_pad(LOGR, TL)>;" in src
+    return 1 << (tl - logr) if tl == 10 and logr >= 7 else -1
+
+
+def tensor_geo(logr, tl):
+    return geo(logr, tl, tensor_xpad_table()[(logr, tl)], tensor_pad(logr, tl))
+
+
 def tensor_xpad_table():
     """tib_xpad(logr, tl) as written in tensor.hip."""
     src = open(os.path.join(CSRC, "tensor.hip")).read()
@@ -116,7 +130,7 @@ def tensor_xpad_table():
 def test_rule_matches_the_header():
     """The layout rule restated above is the one ntt_core.h compiles."""
     src = " ".join(open(os.path.join(CSRC, "ntt_core.h")).read().split())
-    for text in ("static constexpr int PAD = COLS + (32 >> (LOGR - RB0));",
+    for text in ("static constexpr int PAD = PD >= 0 ? PD : COLS + (32 >> (LOGR - RB0));",
                  "static constexpr int XPAD = XP >= 0 ? XP : (COLS >= 32 ? 0 : COLS);",
                  "static constexpr int BP = (PAD << RB1) + XPAD;",
                  "static constexpr int LDS_WORDS = BP << RB0;",
@@ -126,10 +140,10 @@ def test_rule_matches_the_header():
 
 
 def test_layout_is_one_to_one():
-    cases = [(lr, 13, 0) for lr in (5, 6, 7, 8)] + [(lr, 10, -1) for lr in (6, 7, 8)]
-    cases += [(lr, tl, xp) for (lr, tl), xp in tensor_xpad_table().items()]
-    for logr, tl, xp in cases:
-        g = geo(logr, tl, xp)
+    cases = [(lr, 13, 0, -1) for lr in (5, 6, 7, 8)] + [(lr, 10, -1, -1) for lr in (6, 7, 8)]
+    cases += [(lr, tl, xp, tensor_pad(lr, tl)) for (lr, tl), xp in tensor_xpad_table().items()]
+    for logr, tl, xp, pd in cases:
+        g = geo(logr, tl, xp, pd)
         seen = {addr(g, r, c) for r in range(1 << logr) for c in range(g["cols"])}
         assert len(seen) == (1 << logr) * g["cols"], (logr, tl, xp)
         assert max(seen) < g["words"], (logr, tl, xp)
@@ -160,14 +174,21 @@ def test_key_product_tiles_conflict_free(logr):
 
 @pytest.mark.parametrize("logr,tl", [(lr, tl) for lr in (6, 7, 8) for tl in (10, 11, 12)])
 def test_tensor_tiles_at_most_two_way(logr, tl):
-    g = geo(logr, tl, tensor_xpad_table()[(logr, tl)])
-    assert strided(g, tl, 256, True) == 1
+    g = tensor_geo(logr, tl)
+    if tensor_pad(logr, tl) >= 0:
+        # unpadded rows: the tile takes 1024 + 2^RB0 XPAD words, and every
+        # access pattern has at most two lanes of a half-wave on one bank
+        assert g["pad"] == g["cols"] and g["words"] == 1024 + (g["bp"] - (g["pad"] << g["rb1"])) * (1 << g["rb0"])
+        assert g["words"] < geo(logr, tl, 0)["words"] * 0.75
+        assert strided(g, tl, 256, True) <= 2
+    else:
+        assert strided(g, tl, 256, True) == 1
     assert consecutive(g, tl, 256) <= 2
     assert product_stores(g, logr, tl, 256) <= 2
-    # fewer conflicts than plain rows of PAD words
+    # fewer conflicts than rows of the same pitch with no extra block pitch
     plain = dict(g, bp=g["pad"] << g["rb1"])
-    assert consecutive(g, tl, 256) + product_stores(g, logr, tl, 256) < \
-        consecutive(plain, tl, 256) + product_stores(plain, logr, tl, 256)
+    ours = strided(g, tl, 256, True) + consecutive(g, tl, 256) + product_stores(g, logr, tl, 256)
+    assert ours < strided(plain, tl, 256, True) + consecutive(plain, tl, 256) + product_stores(plain, logr, tl, 256)
 
 
 def tw_pos(rb0, sl, rr):
