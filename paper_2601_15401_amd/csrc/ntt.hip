@@ -345,7 +345,7 @@ __device__ __forceinline__ void modup_a2_body(__amdgpu_buffer_rsrc_t src, int na
   for (int i = 0; i < R1::NI; i++) {
     int c, rb, hi;
     R1::decode(i * kModupThreads + tid, c, rb, hi);
-    // the second target's round 1 runs here: its twiddles are not live
+    // the second target's first round runs here: its twiddles are not live
     // through the first target's pass
     item_bfly<R1::RB, true, LAZY, false>(y1[i], tw1, R1::SL0, 0, hi, 0, q1, nf);
     store_lds<R1, G>(y1[i], lds, c, rb);
@@ -470,8 +470,8 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
   const bool transforms = A.B > 1 || e >= A.level;
   if (transforms) stage_tw_pass_b<G::COLS, LOGR, kKipThreads, G::RB0>(ltw, tw, s0, col0);
   // pairs p = (t - 2) B + b.  A pair is "own" when limb e belongs to digit b:
-  // its ModUp image is D_t itself (NTT domain, round-2 layout); otherwise the
-  // pass-A output X_{t,b,e} is read in round-1 layout.
+  // its ModUp image is D_t itself (NTT domain, second-round layout); otherwise the
+  // pass-A output X_{t,b,e} is read in first-round layout.
   // A pair's position (t - 2, b) advances by counting, not by dividing
   // the pair index by B.
   struct Pos {
@@ -520,7 +520,7 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
       }
     }
   };
-  // both key words of every round-2 position of this thread
+  // both key words of every second-round position of this thread
   auto fetch_k = [&](Pos u, uint4 (&kv)[V / 2]) {
     const uint32_t* k0p = evk_e + (((size_t)u.t2 * A.dnum + u.b) * 2) * (size_t)A.key_poly;
     const uint32_t* k1p = k0p + A.key_poly;
@@ -544,7 +544,7 @@ __device__ __forceinline__ void kip_b_body(const uint32_t* Xe, const uint32_t* D
     l0[j] = l1[j] = 0;
     h0[j] = h1[j] = 0;
   }
-  if (sums) {  // the own-digit sums (residues mod q), in round-2 layout
+  if (sums) {  // the own-digit sums (residues mod q), in second-round layout
 #pragma unroll
     for (int i = 0; i < R2::NI; i++) {
       int c, rb, hi;
