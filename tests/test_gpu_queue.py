@@ -103,11 +103,15 @@ def test_queue_drain_and_mixed_streams(sets):
 def test_alternative_schedules_are_exact(ln, L, K, dnum):
     prm = mick.Params(ln, L, K, dnum)
     default = mick.schedule(prm)
-    keys = mick.Keys(prm, 5, 4)
+    keys = mick.Keys(prm, 5, 6)
     rng = np.random.default_rng(ln)
     level = L
     cts = [_rand_ct(rng, prm.q[:level], prm.N) for _ in range(4)]
     want = mick.mul_relin_rescale(prm, keys, cts, level)
+    # six inputs: the fused tensor kernel's 1024-residue tiles, whose row
+    # blocks follow the schedule (2^6, 2^7 or 2^8 rows)
+    cts6 = [_rand_ct(rng, prm.q[:level], prm.N) for _ in range(6)]
+    want6 = mick.mul_relin_rescale(prm, keys, cts6, level)
     op = oparams.make_params(ln, L, K, dnum)
     # two q limbs and the first special prime (prime index L)
     mods, psis = [op.q[0], op.q[1], op.p[0]], [op.psi_q[0], op.psi_q[1], op.psi_p[0]]
@@ -128,6 +132,8 @@ def test_alternative_schedules_are_exact(ln, L, K, dnum):
         assert np.array_equal(got_i, limbs), "schedule %d inverse" % a
         got = mick.mul_relin_rescale(prm, keys, cts, level)
         assert torch.equal(got, want), "schedule %d multiply" % a
+        got6 = mick.mul_relin_rescale(prm, keys, cts6, level)
+        assert torch.equal(got6, want6), "schedule %d six-input multiply" % a
     mick.set_schedule(prm, default)
     with pytest.raises(mick.MickError):
         mick.set_schedule(prm, 6)
